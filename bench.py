@@ -1,0 +1,184 @@
+"""Benchmark of the relativistic lattice Boltzmann time step on one MI355X.
+
+Workload (default): the 2D periodic Taylor-Green-type vortex, 1024 x 1024
+sites, zeta = m/T_R = 1 (44 population classes), peak speed 0.3, 1% noise on
+n and T, tau = 1, the full 2000-step horizon.  The headline path stores
+populations as float32 deviations from a rest-frame equilibrium (float64
+Landau frame, EOS and projections).  The plain float64 path and the scaled
+float16 path are timed on the same workload for comparison.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ELEM = {"fp64": 8, "fp32": 4, "fp16": 2}
+STEP_KERNEL_SOURCES = ["paper_1703_04605_amd/csrc/rlbm_lib.hip", "paper_1703_04605_amd/csrc/rlbm_device.h",
+                       "paper_1703_04605_amd/csrc/rlbm_tables.h"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in STEP_KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision, nx, ny):
+    """HBM bytes per launch of the step kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    e = d.get("entries", {}).get(f"{precision}_{nx}x{ny}")
+    return None if e is None else e.get("hbm_bytes_per_launch")
+
+
+def time_path(st, fields, precision, steps, warmup, tau=1.0):
+    import torch
+    from paper_1703_04605_amd import rlbm
+    s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=2, precision=precision)
+    s.init_fields(*fields, tau=tau)
+    s.step(warmup)
+    s.health(reset=True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    s.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    h = s.health()
+    return s, ms, wall, h
+
+
+def cpu_baseline(st, nx, target_s=12.0):
+    """The FP64 oracle (numpy, one thread) on a bounded sample of the same
+    workload: a 64-row strip of the lattice, as many steps as fit ~target_s."""
+    import numpy as np
+    import workloads
+    from threadpoolctl import threadpool_limits
+    from oracle import lattice as L
+    rows = 64
+    n, T, ux, uy = workloads.taylor_green(nx, nx, seed=0)
+    with threadpool_limits(limits=1):
+        ps = L.build_stencil(st["bases"], st["zeta"], st["v0"], mode="projected", dim=2)
+        m = L.Model(ps, nx, rows, tau=1.0)
+        m.init_equilibrium(n[:rows], T[:rows], ux[:rows], uy[:rows])
+        t0 = time.perf_counter()
+        steps = 0
+        while time.perf_counter() - t0 < target_s or steps == 0:
+            m.step(1)
+            steps += 1
+        dt = time.perf_counter() - t0
+    return {"value": nx * rows * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": f"{nx}x{rows} strip of the {nx}x{nx} workload, {steps} steps, projected classes, "
+                      f"numpy float64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--size", type=int, default=1024)
+    ap.add_argument("--stencil", default="zeta1")
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the other precision paths")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads
+    from tests.helpers import to_dev
+
+    st = workloads.STENCILS[args.stencil]
+    nx = ny = args.size
+    fields = to_dev(workloads.taylor_green(nx, ny, seed=0))
+
+    s, ms, wall, h = time_path(st, fields, args.precision, args.steps, args.warmup)
+    q = s.info["q"]
+    sites = nx * ny
+    ms_step = ms / args.steps
+    mlups = sites * args.steps / (ms * 1e-3) / 1e6
+    alg_bytes = 2 * q * ELEM[args.precision] * sites
+    achieved = alg_bytes / (ms_step * 1e-3) / 1e9
+    traffic = measured_traffic(args.precision, nx, ny)
+    out_hp = {k: v.cpu().numpy() for k, v in s.moments().items()}
+    iters_mean = h["iter_sum"] / (sites * args.steps)
+    del s
+
+    paths = {args.precision: {"mlups": mlups, "ms_per_step": ms_step, "hbm_frac": achieved / HBM_PEAK_GBS,
+                              "landau_iter_mean": iters_mean, "landau_iter_max": h["iter_max"],
+                              "health_flags": h["flags"]}}
+    if not args.no_compare:
+        for p in ("fp64", "fp32", "fp16"):
+            if p == args.precision:
+                continue
+            s2, ms2, _, h2 = time_path(st, fields, p, args.steps, args.warmup)
+            m2 = sites * args.steps / (ms2 * 1e-3) / 1e6
+            ab = 2 * q * ELEM[p] * sites / (ms2 / args.steps * 1e-3) / 1e9
+            o2 = {k: v.cpu().numpy() for k, v in s2.moments().items()}
+            paths[p] = {"mlups": m2, "ms_per_step": ms2 / args.steps, "hbm_frac": ab / HBM_PEAK_GBS,
+                        "landau_iter_mean": h2["iter_sum"] / (sites * args.steps),
+                        "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"]}
+            if p == "fp64":
+                # deviation of the headline path from the float64 GPU path (itself
+                # parity-tested against the oracle) after the full horizon
+                paths[args.precision]["max_rel_err_vs_fp64_path"] = {
+                    k: float(np.abs(out_hp[k] - o2[k]).max() / np.abs(o2[k]).max())
+                    for k in ("n", "eps", "T", "P", "ux", "uy")}
+            del s2
+        if "fp64" in paths:
+            paths["speedup_vs_fp64"] = mlups / paths["fp64"]["mlups"]
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(st, nx)
+    res = {
+        "metric": "MLUPS (site updates per second / 1e6) of the RLBM time step",
+        "value": mlups,
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": f"taylor_green_{nx}x{ny}_{args.stencil}", "nx": nx, "ny": ny,
+                   "zeta": st["zeta"], "v0": st["v0"], "population_classes": q,
+                   "storage": {"fp64": "float64", "fp32": "float32 deviation",
+                               "fp16": "scaled float16 deviation"}[args.precision],
+                   "tau": 1.0, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "cpu_baseline": cpu,
+        "paths": paths,
+        "wall_s_timed_region": wall,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,210 @@
+/*
+ * rlbm.h - C ABI of the MI355X (gfx950) relativistic lattice Boltzmann library.
+ *
+ * The library advances the second-order relativistic lattice Boltzmann method
+ * for particles of finite mass of Gabbana, Mendoza, Succi and Tripiccione,
+ * "Towards a unified lattice kinetic scheme for relativistic hydrodynamics"
+ * (arXiv:1703.04605):
+ *
+ *   f_i(x + n_i, t + 1) = f_i(x, t) - (p_i^mu U_mu)/(p_i^0 tau) (f_i - f_i^eq)
+ *
+ * (Sec. III.B, eq. discrete-relativistic-boltzmann) on 2D (Nx x Ny) and 1D
+ * (Nx x 1) lattices.  Units: T_R = 1 (the temperature unit of Sec. III.A),
+ * lattice spacing 1, time step 1 = dx/v0 (eq. v0dt=dx), so the particle mass
+ * is mbar = m/T_R ("zeta").
+ *
+ * Conventions of every entry point:
+ *   - C linkage, no exceptions cross the ABI; a negative return is an error
+ *     code (RLBM_E*), and rlbm_last_error() gives a message for the context.
+ *   - Pointers marked "device" are HIP device pointers (e.g. torch CUDA tensor
+ *     data_ptr()), pointers marked "host" are ordinary host memory.
+ *   - Field arrays are row-major with x fastest: element (y, x) at y*nx + x.
+ *   - "stream" is a hipStream_t passed as void* (NULL = the default stream).
+ *     Device work is enqueued on it and returns without synchronising, unless
+ *     stated otherwise.
+ *   - Population buffers and field buffers are owned by the caller; the
+ *     library keeps the raw pointers until the next rlbm_init_fields() or
+ *     rlbm_destroy().  The context and its stencil tables are owned by the
+ *     library.  Only rlbm_init_stencil (the constant tables) and
+ *     rlbm_init_fields (a small per-block health array) allocate device
+ *     memory; the time-stepping entry points never do.
+ */
+#ifndef RLBM_H
+#define RLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------- */
+#define RLBM_OK 0
+#define RLBM_EINVAL (-1)      /* invalid argument or size */
+#define RLBM_ENOSTENCIL (-2)  /* no quadrature with all weights positive */
+#define RLBM_EHIP (-3)        /* a HIP runtime call failed */
+#define RLBM_ENUMERIC (-4)    /* a fatal health flag was raised on the GPU */
+#define RLBM_ESTATE (-5)      /* call out of order (e.g. step before init) */
+
+/* ---- storage precisions ---------------------------------------------- */
+#define RLBM_FP64 0      /* populations f_i stored and processed in float64 */
+#define RLBM_FP32_DEV 1  /* f_i = f_i^ref + d_i, d_i stored/processed in float32,
+                            Landau frame, EOS and projections in float64 */
+#define RLBM_FP16_DEV 2  /* d_i = s_i h_i, h_i stored as binary16, arithmetic
+                            as RLBM_FP32_DEV */
+
+/* ---- boundary conditions (per axis) ----------------------------------- */
+#define RLBM_BC_PERIODIC 0
+#define RLBM_BC_OUTFLOW 1  /* zero gradient: a population pulled from outside
+                              the domain takes the post-collision value of the
+                              nearest in-domain site */
+
+/* ---- relaxation time ---------------------------------------------------- */
+#define RLBM_TAU_CONST 0       /* tau (lattice units) constant */
+#define RLBM_TAU_ETA_OVER_S 1  /* tau per site from eta/s (Sec. IV) */
+
+/* ---- health flags (OR-ed over all sites since the last reset) ---------- */
+#define RLBM_H_NAN 1u          /* non-finite moment or field */
+#define RLBM_H_LANDAU 2u       /* Landau iteration hit its cap */
+#define RLBM_H_SUPERLUMINAL 4u /* |u| >= 1 */
+#define RLBM_H_RANGE 8u        /* n <= 0, eps <= 0 or eps/n below the rest mass */
+#define RLBM_H_EOS 16u         /* EOS Newton iteration hit its cap */
+#define RLBM_H_FATAL (RLBM_H_NAN | RLBM_H_SUPERLUMINAL | RLBM_H_RANGE)
+
+typedef struct rlbm_ctx rlbm_ctx;
+
+/*
+ * Stencil description (Sec. III.C-D).  The quadrature is built from
+ * full-symmetric velocity groups (Appendix C): each base vector (a, b, c)
+ * stands for all its coordinate permutations and sign flips.  Abscissae are
+ * p_{i,k} = zeta gamma_k (1, v0 n_{i,k}) (eq. four-momentum); one weight per
+ * group solves the second-order orthonormality conditions (eq. ortho1),
+ * which for full-symmetric groups reduce to six: the energy moments of
+ * order 0..4 of the weight function and one quartic-isotropy condition.
+ */
+typedef struct {
+  int dim;               /* 2: Nx x Ny lattice (1 x Nx x Ny slab of the 3D
+                            stencil), 1: Nx x 1 lattice */
+  int n_groups;          /* number of groups, 6 at second order */
+  const int* group_base; /* host, 3*n_groups ints: base vectors (a, b, c) */
+  double zeta;           /* mbar = m / T_R, > 0 */
+  double v0;             /* > 0: use this v0 (must give positive weights);
+                            <= 0: search [v0_lo, v0_hi] for the interval of
+                            all-positive weights and take its midpoint */
+  double v0_lo, v0_hi;   /* search interval (0, 0: (0, v_max)) */
+  int precision;         /* RLBM_FP64 | RLBM_FP32_DEV | RLBM_FP16_DEV */
+  double n_ref, T_ref;   /* deviation reference f^ref = f^eq(n_ref, T_ref, u=0)
+                            (ignored for RLBM_FP64; 0 means 1) */
+} rlbm_stencil_desc;
+
+typedef struct {
+  int q3;                /* populations of the 3D stencil */
+  int q;                 /* populations after exact in-plane merging (the
+                            number of planes the GPU stores) */
+  double v0;             /* v0 in use */
+  double v0_lo, v0_hi;   /* positive-weight window found (search only) */
+  double weights[16];    /* weight per group (per population of the group) */
+  double ortho_residual; /* max |sum_i w_i J_l(p_i) J_k(p_i) - delta_lk| */
+  int max_shift;         /* max |n_x| (and |n_y| in 2D) of the stencil */
+} rlbm_stencil_info;
+
+/*
+ * Builds the stencil on the host (long double), checks orthonormality and
+ * positivity, and uploads the population-class table to the current HIP
+ * device.  *out receives a new context.  info (host, nullable) receives the
+ * result.  Errors: RLBM_EINVAL (bad description), RLBM_ENOSTENCIL (no
+ * positive weights at v0 / in the window, or orthonormality residual above
+ * 1e-10), RLBM_EHIP.
+ */
+int rlbm_init_stencil(rlbm_ctx** out, const rlbm_stencil_desc* desc, rlbm_stencil_info* info);
+
+/* Host-only part of rlbm_init_stencil (no HIP call): fills info. */
+int rlbm_solve_stencil(const rlbm_stencil_desc* desc, rlbm_stencil_info* info);
+
+/*
+ * Host-only: the population-class table of the stencil.  For class j
+ * (0 <= j < info.q): disp[2j], disp[2j+1] = in-plane displacement (n_x, n_y);
+ * mom[3j..3j+2] = (p^0, p^x, p^y) (p^y = 0 in 1D); M[10j + k] = sum over the
+ * class members of w_i J^(k)(p_i) for the polynomials, in Appendix A labels,
+ * k = 0, 1_0, 1_x, 1_y, 2_00, 2_0x, 2_0y, 2_xx, 2_yy, 2_xy.  Buffers are host
+ * arrays of capacity cap classes; RLBM_EINVAL if cap < q.
+ */
+int rlbm_class_table(const rlbm_stencil_desc* desc, int cap, int* disp, double* mom, double* M);
+
+/* Frees the context and its device tables (after synchronising its work). */
+int rlbm_destroy(rlbm_ctx* ctx);
+
+/* Bytes of one population buffer for an nx x ny lattice in this context's
+ * precision (planes padded to 256 bytes).  0 on invalid sizes. */
+size_t rlbm_population_bytes(const rlbm_ctx* ctx, int nx, int ny);
+
+typedef struct {
+  int nx, ny;            /* lattice size; ny must be 1 when dim == 1 */
+  int bc_x, bc_y;        /* RLBM_BC_* */
+  int tau_mode;          /* RLBM_TAU_* */
+  double tau;            /* RLBM_TAU_CONST: relaxation time (> 0.5) */
+  /* RLBM_TAU_ETA_OVER_S (Sec. IV): tau = 1/2 + (3/2) (eta/s) s hbar_c v0 / (P dx)
+   * with s = 4n - n ln(n / n_eq), n_eq = 16 T^3 / (pi^2 (hbar c)^3), in
+   * physical units: T = T_lat * T_R_GeV, n = n_lat * n_unit_fm3. */
+  double eta_over_s, T_R_GeV, n_unit_fm3, dx_fm;
+  double landau_tol;     /* stop when |d eps| <= tol eps (0: 1e-14 for FP64,
+                            1e-10 otherwise) */
+  int landau_maxit;      /* iteration cap (0: 200) */
+} rlbm_lattice_desc;
+
+/*
+ * Sets f_i(x, 0) = f_i^eq(n, T, u) (eq. mj-discrete-feq with the density n
+ * factored in) at every site from caller fields n, T, ux, uy (device, float64,
+ * nx*ny each).  popA and popB (device, pop_bytes each, at least
+ * rlbm_population_bytes()) become the ping-pong state.  The step counter is
+ * reset and the health flags cleared.  Errors: RLBM_EINVAL, RLBM_EHIP.
+ */
+int rlbm_init_fields(rlbm_ctx* ctx, const rlbm_lattice_desc* lat, const double* n, const double* T,
+                     const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
+                     void* stream);
+
+/*
+ * Advances nsteps time steps (collide, then stream; eq.
+ * discrete-relativistic-boltzmann): per site, moments N^a, T^ab
+ * (eq. mj-discrete-second-moment), Landau frame (eqs. landau-lifshitz-*),
+ * EOS inversion (eq. relativistic-eos), projections (Appendix B), equilibrium
+ * (eq. mj-discrete-feq), Anderson-Witting relaxation and exact streaming.
+ * Asynchronous on stream; launch errors are returned at once (RLBM_EHIP).
+ * Health flags accumulate on the device (rlbm_get_health).
+ */
+int rlbm_step(rlbm_ctx* ctx, int nsteps, void* stream);
+
+/*
+ * Writes the macroscopic fields of the current (pre-collision) state f(x, t):
+ * n, eps, T, P = nT, ux, uy (device float64, nx*ny each, any may be NULL) and
+ * raw9 (device float64 [9][ny][nx] or NULL): N^0, N^x, N^y, T^00, T^0x,
+ * T^0y, T^xx, T^xy, T^yy.
+ */
+int rlbm_moments(rlbm_ctx* ctx, double* n, double* eps, double* T, double* P, double* ux, double* uy,
+                 double* raw9, void* stream);
+
+/* Synchronises stream, returns the OR of the health flags in *flags (host)
+ * and the Landau iteration statistics (sum over sites and max since the
+ * last reset, host, nullable); RLBM_ENUMERIC if a fatal flag is set.
+ * reset != 0 clears them afterwards. */
+int rlbm_get_health(rlbm_ctx* ctx, unsigned* flags, unsigned long long* landau_iter_sum,
+                    unsigned* landau_iter_max, int reset, void* stream);
+
+/* Completed time steps since rlbm_init_fields. */
+long long rlbm_step_count(const rlbm_ctx* ctx);
+
+/* Copies the current state (population planes in storage precision, as laid
+ * out by the library) to dst (device or host, pop_bytes) and back; with the
+ * step count this is the whole state (checkpoint / resume). */
+int rlbm_save_state(rlbm_ctx* ctx, void* dst, size_t bytes, long long* step, int* layout_flag, void* stream);
+int rlbm_load_state(rlbm_ctx* ctx, const void* src, size_t bytes, long long step, int layout_flag, void* stream);
+
+/* Last error message of ctx (or of the last failed context-less call when
+ * ctx is NULL).  The string is owned by the library. */
+const char* rlbm_last_error(const rlbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLBM_H */

@@ -1,0 +1,550 @@
+// HIP kernels (gfx950) and C ABI of the relativistic lattice Boltzmann library
+// (arXiv:1703.04605, second-order model of Sec. III).
+//
+// Data layout in HBM: one plane per population class j, planes[j][y][x],
+// x fastest, planes padded to 128 elements; two buffers (ping-pong).
+// A time step is one fused kernel: each thread owns one site, pulls the Q
+// class values f_j(x - n_j) from the previous post-collision state (exact
+// streaming, Sec. III.B), keeps them in registers, reduces the nine in-plane
+// moments, solves the Landau frame, inverts the equation of state, builds the
+// equilibrium from the projections and relaxes (Anderson-Witting), and writes
+// the post-collision values to the other buffer.  Each population value is
+// read once and written once per step, which is the HBM roofline of the step.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+#include <vector>
+
+#include "../../include/rlbm.h"
+#include "rlbm_device.h"
+#include "rlbm_stencil.h"
+#include "rlbm_tables.h"
+
+namespace rlbm {
+
+constexpr int kBlock = 256;
+constexpr long long kPlaneAlign = 128;  // elements
+constexpr double kHbarC = 0.1973269804; // GeV fm
+
+template <int P> struct Traits;
+template <> struct Traits<RLBM_FP64> { using S = double; using A = double; };
+template <> struct Traits<RLBM_FP32_DEV> { using S = float; using A = float; };
+template <> struct Traits<RLBM_FP16_DEV> { using S = _Float16; using A = float; };
+
+template <int P>
+__device__ __forceinline__ typename Traits<P>::A to_arith(typename Traits<P>::S v, const RlbmTable* tb, int j) {
+  if constexpr (P == RLBM_FP16_DEV) return (float)v * tb->scale[j];
+  else return v;
+}
+
+template <int P>
+__device__ __forceinline__ typename Traits<P>::S to_store(typename Traits<P>::A v, const RlbmTable* tb, int j) {
+  if constexpr (P == RLBM_FP16_DEV) return (_Float16)(v * tb->inv_scale[j]);
+  else return v;
+}
+
+// Reduces health flags and Landau iteration counts over the block into the
+// block's own slot (one slot per logical block: no atomics, no races).
+__device__ __forceinline__ void block_stats(RlbmSlot* slots, int lb, unsigned flags, unsigned iters) {
+  __shared__ unsigned s_f[kBlock / 64], s_m[kBlock / 64], s_s[kBlock / 64];
+  unsigned fl = flags, mx = iters, sm = iters;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    fl |= __shfl_xor(fl, off);
+    mx = max(mx, (unsigned)__shfl_xor(mx, off));
+    sm += __shfl_xor(sm, off);
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_f[w] = fl;
+    s_m[w] = mx;
+    s_s[w] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < kBlock / 64; ++i) {
+      fl |= s_f[i];
+      mx = max(mx, s_m[i]);
+      sm += s_s[i];
+    }
+    RlbmSlot s = slots[lb];
+    s.flags |= fl;
+    s.iter_max = max(s.iter_max, mx);
+    s.iter_sum += sm;
+    slots[lb] = s;
+  }
+}
+
+// Macroscopic state of one site from its moments (float64).
+struct Macro {
+  double n, eps, T, P, ux, uy, gamma, R;
+  int iters;
+  unsigned flags;
+};
+
+__device__ __forceinline__ Macro macroscopic(const RlbmConsts& c, double N0, double Nx, double Ny, double T00,
+                                             double T0x, double T0y, double Txx, double Txy, double Tyy,
+                                             double tol, int maxit) {
+  Macro m;
+  m.flags = 0;
+  m.ux = 0.0;
+  m.uy = 0.0;
+  m.iters = landau_solve(T00, T0x, T0y, Txx, Txy, Tyy, tol, maxit, m.eps, m.ux, m.uy);
+  if (m.iters > maxit) m.flags |= RLBM_H_LANDAU;
+  const double u2 = m.ux * m.ux + m.uy * m.uy;
+  if (!(u2 < 1.0)) m.flags |= RLBM_H_SUPERLUMINAL;
+  m.gamma = 1.0 / sqrt(1.0 - u2);
+  m.n = m.gamma * (N0 - m.ux * Nx - m.uy * Ny);
+  if (!(m.n > 0.0) || !(m.eps > 0.0)) m.flags |= RLBM_H_RANGE;
+  m.T = eos_temperature(m.eps / m.n, c.zeta, m.flags);
+  m.P = m.n * m.T;
+  m.R = k1k2_ratio(c.zeta / m.T);
+  if (!isfinite(m.T) || !isfinite(m.eps) || !isfinite(m.n) || !isfinite(m.R)) m.flags |= RLBM_H_NAN;
+  return m;
+}
+
+// ------------------------------------------------------------------ step
+
+template <int QCAP, int P>
+__global__ void __launch_bounds__(kBlock) k_step(RlbmStepArgs a) {
+  using S = typename Traits<P>::S;
+  using A = typename Traits<P>::A;
+  const RlbmTable* __restrict__ tb = a.tab;
+  const int Q = tb->c.Q;
+  const int lb = xcd_remap(blockIdx.x, gridDim.x);
+  const int y = lb / a.blocks_x;
+  const int x = (lb - y * a.blocks_x) * kBlock + threadIdx.x;
+  const bool active = x < a.nx;
+  const int xs = active ? x : a.nx - 1;
+  const S* __restrict__ src = (const S*)a.src;
+  S* __restrict__ dst = (S*)a.dst;
+
+  A f[QCAP];
+#pragma unroll
+  for (int j = 0; j < QCAP; ++j) {
+    if (j < Q) {
+      int sx = xs, sy = y;
+      if (a.shift) {
+        sx = wrap_or_clamp(xs - tb->nx[j], a.nx, a.bc_x, a.x_small);
+        sy = wrap_or_clamp(y - tb->ny[j], a.ny, a.bc_y, a.y_small);
+      }
+      f[j] = to_arith<P>(src[(long long)j * a.plane + (long long)sy * a.nx + sx], tb, j);
+    } else {
+      f[j] = A(0);
+    }
+  }
+
+  // moments (eq. mj-discrete-second-moment); deviation modes add the exact
+  // float64 moments of the reference state
+  A m[9] = {A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0)};
+#pragma unroll
+  for (int j = 0; j < QCAP; ++j) {
+    if (j < Q) {
+      A p0, px, py;
+      if constexpr (P == RLBM_FP64) {
+        p0 = tb->p0[j]; px = tb->px[j]; py = tb->py[j];
+      } else {
+        p0 = tb->fp0[j]; px = tb->fpx[j]; py = tb->fpy[j];
+      }
+      const A a0 = f[j] * p0, ax = f[j] * px, ay = f[j] * py;
+      m[0] += a0; m[1] += ax; m[2] += ay;
+      m[3] = fma(a0, p0, m[3]); m[4] = fma(a0, px, m[4]); m[5] = fma(a0, py, m[5]);
+      m[6] = fma(ax, px, m[6]); m[7] = fma(ax, py, m[7]); m[8] = fma(ay, py, m[8]);
+    }
+  }
+  double md[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) md[k] = (P == RLBM_FP64) ? (double)m[k] : tb->c.ref_mom[k] + (double)m[k];
+
+  Macro mac = macroscopic(tb->c, md[0], md[1], md[2], md[3], md[4], md[5], md[6], md[7], md[8], a.landau_tol,
+                          a.landau_maxit);
+  const double tau = a.tau_mode == RLBM_TAU_CONST ? a.tau : tau_eta_over_s(a.tk1, a.tk2, mac.n, mac.T);
+  double b[RLBM_NB];
+  projections(tb->c, mac.T, mac.R, mac.gamma, mac.gamma * mac.ux, mac.gamma * mac.uy, b);
+  // Anderson-Witting frequency p_i.U/(p_i^0 tau) = gamma (1 - v0 n_i.u)/tau (eq. discrete-relativistic-boltzmann)
+  const double w0 = mac.gamma / tau;
+  const double wx = -w0 * tb->c.v0 * mac.ux, wy = -w0 * tb->c.v0 * mac.uy;
+  A nb[RLBM_NB];
+#pragma unroll
+  for (int k = 0; k < RLBM_NB; ++k) nb[k] = (A)(mac.n * b[k] - (P == RLBM_FP64 ? 0.0 : tb->c.nb_ref[k]));
+  const A W0 = (A)w0, WX = (A)wx, WY = (A)wy;
+
+  const long long o = (long long)y * a.nx + xs;
+#pragma unroll
+  for (int j = 0; j < QCAP; ++j) {
+    if (j < Q) {
+      A feq, dx, dy;
+      if constexpr (P == RLBM_FP64) {
+        feq = nb[0] * tb->M[0][j];
+#pragma unroll
+        for (int k = 1; k < RLBM_NB; ++k) feq = fma(nb[k], tb->M[k][j], feq);
+        dx = tb->dnx[j]; dy = tb->dny[j];
+      } else {
+        feq = nb[0] * tb->Mf[0][j];
+#pragma unroll
+        for (int k = 1; k < RLBM_NB; ++k) feq = fma(nb[k], tb->Mf[k][j], feq);
+        dx = tb->fnx[j]; dy = tb->fny[j];
+      }
+      const A om = fma(WY, dy, fma(WX, dx, W0));
+      const A out = fma(-om, f[j] - feq, f[j]);
+      if (active) dst[(long long)j * a.plane + o] = to_store<P>(out, tb, j);
+    }
+  }
+  block_stats(a.slots, lb, active ? mac.flags : 0u, active ? (unsigned)mac.iters : 0u);
+}
+
+// ------------------------------------------------------------------ moments
+
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_moments(RlbmMomArgs a) {
+  using S = typename Traits<P>::S;
+  const RlbmTable* __restrict__ tb = a.tab;
+  const long long site = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (site >= (long long)a.nx * a.ny) return;
+  const int y = (int)(site / a.nx), x = (int)(site - (long long)y * a.nx);
+  const S* __restrict__ src = (const S*)a.src;
+  double m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < tb->c.Q; ++j) {
+    int sx = x, sy = y;
+    if (a.shift) {
+      sx = wrap_or_clamp(x - tb->nx[j], a.nx, a.bc_x, a.x_small);
+      sy = wrap_or_clamp(y - tb->ny[j], a.ny, a.bc_y, a.y_small);
+    }
+    const double f = (double)to_arith<P>(src[(long long)j * a.plane + (long long)sy * a.nx + sx], tb, j);
+    const double p0 = tb->p0[j], px = tb->px[j], py = tb->py[j];
+    m[0] += f * p0; m[1] += f * px; m[2] += f * py;
+    m[3] += f * p0 * p0; m[4] += f * p0 * px; m[5] += f * p0 * py;
+    m[6] += f * px * px; m[7] += f * px * py; m[8] += f * py * py;
+  }
+  if (P != RLBM_FP64)
+    for (int k = 0; k < 9; ++k) m[k] += tb->c.ref_mom[k];
+  Macro mac = macroscopic(tb->c, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[8], a.landau_tol,
+                          a.landau_maxit);
+  if (a.n) a.n[site] = mac.n;
+  if (a.eps) a.eps[site] = mac.eps;
+  if (a.T) a.T[site] = mac.T;
+  if (a.P) a.P[site] = mac.P;
+  if (a.ux) a.ux[site] = mac.ux;
+  if (a.uy) a.uy[site] = mac.uy;
+  if (a.raw9) {
+    const long long S2 = (long long)a.nx * a.ny;
+    for (int k = 0; k < 9; ++k) a.raw9[k * S2 + site] = m[k];
+  }
+}
+
+// ------------------------------------------------------------------ init
+
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_init(RlbmInitArgs a) {
+  using S = typename Traits<P>::S;
+  const RlbmTable* __restrict__ tb = a.tab;
+  const long long site = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (site >= (long long)a.nx * a.ny) return;
+  const double n = a.n[site], T = a.T[site], ux = a.ux[site], uy = a.uy[site];
+  const double g = 1.0 / sqrt(1.0 - ux * ux - uy * uy);
+  double b[RLBM_NB];
+  projections(tb->c, T, k1k2_ratio(tb->c.zeta / T), g, g * ux, g * uy, b);
+  double nb[RLBM_NB];
+  for (int k = 0; k < RLBM_NB; ++k) nb[k] = n * b[k] - (P == RLBM_FP64 ? 0.0 : tb->c.nb_ref[k]);
+  S* __restrict__ dst = (S*)a.dst;
+  for (int j = 0; j < tb->c.Q; ++j) {
+    double fe = 0.0;
+    for (int k = 0; k < RLBM_NB; ++k) fe = fma(nb[k], tb->M[k][j], fe);
+    dst[(long long)j * a.plane + site] = to_store<P>((typename Traits<P>::A)fe, tb, j);
+  }
+}
+
+// ------------------------------------------------------------------ dispatch
+
+using StepFn = void (*)(RlbmStepArgs);
+constexpr int kQcaps[] = {24, 48, 80, 160};
+
+template <int P>
+StepFn step_kernel(int Q) {
+  if (Q <= 24) return k_step<24, P>;
+  if (Q <= 48) return k_step<48, P>;
+  if (Q <= 80) return k_step<80, P>;
+  return k_step<160, P>;
+}
+
+StepFn select_step(int prec, int Q) {
+  switch (prec) {
+    case RLBM_FP64: return step_kernel<RLBM_FP64>(Q);
+    case RLBM_FP32_DEV: return step_kernel<RLBM_FP32_DEV>(Q);
+    default: return step_kernel<RLBM_FP16_DEV>(Q);
+  }
+}
+
+size_t elem_size(int prec) { return prec == RLBM_FP64 ? 8 : prec == RLBM_FP32_DEV ? 4 : 2; }
+
+}  // namespace rlbm
+
+using namespace rlbm;
+
+struct rlbm_ctx {
+  RlbmTable* h_tab = nullptr;
+  RlbmTable* d_tab = nullptr;
+  rlbm_stencil_info info;
+  int device = 0;
+  bool have_fields = false;
+  rlbm_lattice_desc lat;
+  void* buf[2] = {nullptr, nullptr};
+  size_t pop_bytes = 0;
+  long long plane = 0;
+  int cur = 0;
+  int shifted = 0;
+  long long steps = 0;
+  RlbmSlot* d_slots = nullptr;
+  int nblocks = 0, blocks_x = 0;
+  double tk1 = 0, tk2 = 0;
+  char err[512] = {0};
+};
+
+static int fail(rlbm_ctx* c, int code, const char* fmt, const char* detail = "") {
+  char msg[512];
+  snprintf(msg, sizeof(msg), fmt, detail);
+  if (c) snprintf(c->err, sizeof(c->err), "%s", msg);
+  rlbm_set_global_error(msg);
+  return code;
+}
+
+#define HIPCHECK(ctx, call)                                                  \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) return fail(ctx, RLBM_EHIP, "HIP error: %s", hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" int rlbm_init_stencil(rlbm_ctx** out, const rlbm_stencil_desc* desc, rlbm_stencil_info* info) {
+  if (!out) return fail(nullptr, RLBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  rlbm_ctx* c = new rlbm_ctx();
+  c->h_tab = new RlbmTable();
+  char err[512] = {0};
+  int rc = rlbm_build_table(desc, &c->info, c->h_tab, err, sizeof(err));
+  if (rc) {
+    fail(nullptr, rc, "%s", err);
+    delete c->h_tab;
+    delete c;
+    return rc;
+  }
+  hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->d_tab, sizeof(RlbmTable));
+  if (e == hipSuccess) e = hipMemcpy(c->d_tab, c->h_tab, sizeof(RlbmTable), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    fail(nullptr, RLBM_EHIP, "HIP error: %s", hipGetErrorString(e));
+    if (c->d_tab) (void)hipFree(c->d_tab);
+    delete c->h_tab;
+    delete c;
+    return RLBM_EHIP;
+  }
+  if (info) *info = c->info;
+  *out = c;
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_destroy(rlbm_ctx* c) {
+  if (!c) return RLBM_OK;
+  (void)hipDeviceSynchronize();
+  if (c->d_tab) (void)hipFree(c->d_tab);
+  if (c->d_slots) (void)hipFree(c->d_slots);
+  delete c->h_tab;
+  delete c;
+  return RLBM_OK;
+}
+
+static long long plane_elems(int nx, int ny) {
+  long long s = (long long)nx * ny;
+  return (s + kPlaneAlign - 1) / kPlaneAlign * kPlaneAlign;
+}
+
+extern "C" size_t rlbm_population_bytes(const rlbm_ctx* c, int nx, int ny) {
+  if (!c || nx <= 0 || ny <= 0) return 0;
+  return (size_t)c->h_tab->c.Q * (size_t)plane_elems(nx, ny) * elem_size(c->h_tab->c.precision);
+}
+
+extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n, const double* T,
+                                const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
+                                void* stream) {
+  if (!c || !lat) return fail(c, RLBM_EINVAL, "NULL context or lattice");
+  const RlbmConsts& k = c->h_tab->c;
+  if (lat->nx <= 0 || lat->ny <= 0 || (k.dim == 1 && lat->ny != 1))
+    return fail(c, RLBM_EINVAL, "invalid lattice size (1D stencils need ny == 1)");
+  if ((long long)lat->nx * lat->ny > (1LL << 31) - 1) return fail(c, RLBM_EINVAL, "lattice too large");
+  if (lat->bc_x < 0 || lat->bc_x > 1 || lat->bc_y < 0 || lat->bc_y > 1) return fail(c, RLBM_EINVAL, "invalid bc");
+  if (lat->tau_mode == RLBM_TAU_CONST) {
+    if (!(lat->tau > 0.5)) return fail(c, RLBM_EINVAL, "tau must exceed 1/2");
+  } else if (lat->tau_mode == RLBM_TAU_ETA_OVER_S) {
+    if (!(lat->eta_over_s > 0) || !(lat->T_R_GeV > 0) || !(lat->n_unit_fm3 > 0) || !(lat->dx_fm > 0))
+      return fail(c, RLBM_EINVAL, "eta/s mode needs eta_over_s, T_R_GeV, n_unit_fm3, dx_fm > 0");
+  } else {
+    return fail(c, RLBM_EINVAL, "invalid tau mode");
+  }
+  if (!n || !T || !ux || !uy || !popA || !popB || popA == popB)
+    return fail(c, RLBM_EINVAL, "NULL field or population buffer");
+  size_t need = rlbm_population_bytes(c, lat->nx, lat->ny);
+  if (pop_bytes < need) return fail(c, RLBM_EINVAL, "population buffer too small");
+  hipStream_t s = (hipStream_t)stream;
+
+  c->lat = *lat;
+  if (!(c->lat.landau_tol > 0)) c->lat.landau_tol = k.precision == RLBM_FP64 ? 1e-14 : 1e-10;
+  if (c->lat.landau_maxit <= 0) c->lat.landau_maxit = 200;
+  c->buf[0] = popA;
+  c->buf[1] = popB;
+  c->pop_bytes = pop_bytes;
+  c->plane = plane_elems(lat->nx, lat->ny);
+  c->cur = 0;
+  c->shifted = 0;
+  c->steps = 0;
+  c->blocks_x = (lat->nx + kBlock - 1) / kBlock;
+  int nb = c->blocks_x * lat->ny;
+  if (nb != c->nblocks) {
+    if (c->d_slots) HIPCHECK(c, hipFree(c->d_slots));
+    c->d_slots = nullptr;
+    HIPCHECK(c, hipMalloc((void**)&c->d_slots, sizeof(RlbmSlot) * nb));
+    c->nblocks = nb;
+  }
+  HIPCHECK(c, hipMemsetAsync(c->d_slots, 0, sizeof(RlbmSlot) * nb, s));
+  if (lat->tau_mode == RLBM_TAU_ETA_OVER_S) {
+    const double TR = lat->T_R_GeV;
+    c->tk1 = 1.5 * lat->eta_over_s * kHbarC * k.v0 / (lat->dx_fm * TR);
+    c->tk2 = lat->n_unit_fm3 * M_PI * M_PI * kHbarC * kHbarC * kHbarC / (16.0 * TR * TR * TR);
+  }
+  RlbmInitArgs ia;
+  ia.dst = popA;
+  ia.plane = c->plane;
+  ia.nx = lat->nx;
+  ia.ny = lat->ny;
+  ia.n = n; ia.T = T; ia.ux = ux; ia.uy = uy;
+  ia.tab = c->d_tab;
+  long long sites = (long long)lat->nx * lat->ny;
+  dim3 grid((unsigned)((sites + kBlock - 1) / kBlock));
+  switch (k.precision) {
+    case RLBM_FP64: hipLaunchKernelGGL(k_init<RLBM_FP64>, grid, dim3(kBlock), 0, s, ia); break;
+    case RLBM_FP32_DEV: hipLaunchKernelGGL(k_init<RLBM_FP32_DEV>, grid, dim3(kBlock), 0, s, ia); break;
+    default: hipLaunchKernelGGL(k_init<RLBM_FP16_DEV>, grid, dim3(kBlock), 0, s, ia); break;
+  }
+  HIPCHECK(c, hipGetLastError());
+  c->have_fields = true;
+  return RLBM_OK;
+}
+
+static void fill_geometry(const rlbm_ctx* c, int& x_small, int& y_small) {
+  x_small = c->lat.nx <= c->h_tab->c.max_shift ? 1 : 0;
+  y_small = c->lat.ny <= c->h_tab->c.max_shift ? 1 : 0;
+}
+
+extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
+  if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
+  if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_step before rlbm_init_fields");
+  if (nsteps < 0) return fail(c, RLBM_EINVAL, "negative step count");
+  hipStream_t s = (hipStream_t)stream;
+  RlbmStepArgs a;
+  a.plane = c->plane;
+  a.nx = c->lat.nx;
+  a.ny = c->lat.ny;
+  a.bc_x = c->lat.bc_x;
+  a.bc_y = c->lat.bc_y;
+  fill_geometry(c, a.x_small, a.y_small);
+  a.blocks_x = c->blocks_x;
+  a.tau_mode = c->lat.tau_mode;
+  a.tau = c->lat.tau;
+  a.tk1 = c->tk1;
+  a.tk2 = c->tk2;
+  a.landau_tol = c->lat.landau_tol;
+  a.landau_maxit = c->lat.landau_maxit;
+  a.tab = c->d_tab;
+  a.slots = c->d_slots;
+  StepFn fn = select_step(c->h_tab->c.precision, c->h_tab->c.Q);
+  for (int i = 0; i < nsteps; ++i) {
+    a.src = c->buf[c->cur];
+    a.dst = c->buf[1 - c->cur];
+    a.shift = c->shifted;
+    hipLaunchKernelGGL(fn, dim3(c->nblocks), dim3(kBlock), 0, s, a);
+    HIPCHECK(c, hipGetLastError());
+    c->cur ^= 1;
+    c->shifted = 1;
+    c->steps++;
+  }
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_moments(rlbm_ctx* c, double* n, double* eps, double* T, double* P, double* ux, double* uy,
+                            double* raw9, void* stream) {
+  if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
+  if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_moments before rlbm_init_fields");
+  RlbmMomArgs a;
+  a.src = c->buf[c->cur];
+  a.plane = c->plane;
+  a.nx = c->lat.nx;
+  a.ny = c->lat.ny;
+  a.bc_x = c->lat.bc_x;
+  a.bc_y = c->lat.bc_y;
+  a.shift = c->shifted;
+  fill_geometry(c, a.x_small, a.y_small);
+  a.landau_tol = c->lat.landau_tol;
+  a.landau_maxit = c->lat.landau_maxit;
+  a.tab = c->d_tab;
+  a.n = n; a.eps = eps; a.T = T; a.P = P; a.ux = ux; a.uy = uy; a.raw9 = raw9;
+  long long sites = (long long)a.nx * a.ny;
+  dim3 grid((unsigned)((sites + kBlock - 1) / kBlock));
+  hipStream_t s = (hipStream_t)stream;
+  switch (c->h_tab->c.precision) {
+    case RLBM_FP64: hipLaunchKernelGGL(k_moments<RLBM_FP64>, grid, dim3(kBlock), 0, s, a); break;
+    case RLBM_FP32_DEV: hipLaunchKernelGGL(k_moments<RLBM_FP32_DEV>, grid, dim3(kBlock), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_moments<RLBM_FP16_DEV>, grid, dim3(kBlock), 0, s, a); break;
+  }
+  HIPCHECK(c, hipGetLastError());
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_get_health(rlbm_ctx* c, unsigned* flags, unsigned long long* iter_sum, unsigned* iter_max,
+                               int reset, void* stream) {
+  if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
+  if (!c->have_fields) return fail(c, RLBM_ESTATE, "no fields");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCHECK(c, hipStreamSynchronize(s));
+  std::vector<RlbmSlot> h(c->nblocks);
+  HIPCHECK(c, hipMemcpy(h.data(), c->d_slots, sizeof(RlbmSlot) * c->nblocks, hipMemcpyDeviceToHost));
+  unsigned f = 0, mx = 0;
+  unsigned long long sm = 0;
+  for (auto& x : h) {
+    f |= x.flags;
+    mx = mx > x.iter_max ? mx : x.iter_max;
+    sm += x.iter_sum;
+  }
+  if (flags) *flags = f;
+  if (iter_sum) *iter_sum = sm;
+  if (iter_max) *iter_max = mx;
+  if (reset) {
+    HIPCHECK(c, hipMemsetAsync(c->d_slots, 0, sizeof(RlbmSlot) * c->nblocks, s));
+    HIPCHECK(c, hipStreamSynchronize(s));
+  }
+  if (f & RLBM_H_FATAL) return fail(c, RLBM_ENUMERIC, "fatal health flag raised (0x%s)", "see flags");
+  return RLBM_OK;
+}
+
+extern "C" long long rlbm_step_count(const rlbm_ctx* c) { return c ? c->steps : -1; }
+
+extern "C" int rlbm_save_state(rlbm_ctx* c, void* dst, size_t bytes, long long* step, int* layout_flag,
+                               void* stream) {
+  if (!c || !dst || !c->have_fields) return fail(c, RLBM_EINVAL, "invalid save");
+  if (bytes < c->pop_bytes) return fail(c, RLBM_EINVAL, "destination too small");
+  HIPCHECK(c, hipMemcpyAsync(dst, c->buf[c->cur], c->pop_bytes, hipMemcpyDefault, (hipStream_t)stream));
+  if (step) *step = c->steps;
+  if (layout_flag) *layout_flag = c->shifted;
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_load_state(rlbm_ctx* c, const void* src, size_t bytes, long long step, int layout_flag,
+                               void* stream) {
+  if (!c || !src || !c->have_fields) return fail(c, RLBM_EINVAL, "invalid load");
+  if (bytes < c->pop_bytes) return fail(c, RLBM_EINVAL, "source too small");
+  HIPCHECK(c, hipMemcpyAsync(c->buf[c->cur], src, c->pop_bytes, hipMemcpyDefault, (hipStream_t)stream));
+  c->steps = step;
+  c->shifted = layout_flag ? 1 : 0;
+  return RLBM_OK;
+}
+
+extern "C" const char* rlbm_last_error(const rlbm_ctx* c) { return c ? c->err : rlbm_global_error(); }

@@ -1,0 +1,471 @@
+// Host-side construction of the quadrature stencil and of the population-class
+// table (Sec. III.A-D of arXiv:1703.04605), in long double.  No HIP calls.
+//
+//  * Bessel functions K_nu(x) from the integral representation
+//    K_nu(x) = int_0^inf exp(-x cosh t) cosh(nu t) dt (trapezoid rule, which is
+//    spectrally accurate for this even, entire integrand).
+//  * Energy moments of the weight function omega(p0) = exp(-p0)/N_R
+//    (eq. mj-poly-weighting-factor, T_R = 1) in the variable p0 = m cosh t,
+//    where d^3p/p^0 = 4 pi m^2 sinh^2 t dt dOmega/(4 pi).
+//  * Weights: for full-symmetric groups the second-order conditions of
+//    eq. ortho1 reduce to six linear equations in the group weights: the
+//    energy moments sum_k N_k w_k (p0_k)^a = mu_a, a = 0..4, and the quartic
+//    isotropy sum_k w_k sum_{i in k} (p_x^4 - 3 p_x^2 p_y^2) = 0.
+//    All 14 x 14 conditions are then verified explicitly.
+//  * Classes: the 1-thick lattice (Sec. IV: 1 x N x M and 1 x 1 x N) lets
+//    populations of one group with equal in-plane displacement be merged
+//    exactly, because they share p^0, the in-plane momentum and (U_z = 0)
+//    their relaxation frequency.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <array>
+#include <memory>
+#include <map>
+#include <set>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rlbm.h"
+#include "rlbm_stencil.h"
+
+typedef long double ld;
+
+namespace {
+
+ld besselk_ld(int nu, ld x) {
+  const ld h = 1.0L / 32.0L;
+  ld s = 0.5L * expl(-x);
+  for (int k = 1; k < 100000; ++k) {
+    ld t = k * h;
+    ld v = expl(-x * coshl(t)) * coshl(nu * t);
+    s += v;
+    if (v < 1e-24L * s && x * (coshl(t) - 1.0L) > 40.0L) break;
+  }
+  return s * h;
+}
+
+// S_a = int_0^inf exp(-m (cosh t - 1)) cosh^a t sinh^2 t dt, a = 0..4
+void energy_integrals(ld m, ld S[5]) {
+  const ld h = 1.0L / 64.0L;
+  for (int a = 0; a < 5; ++a) S[a] = 0.0L;
+  for (int k = 1; k < 200000; ++k) {
+    ld t = k * h;
+    ld c = coshl(t), sh = sinhl(t);
+    ld e = expl(-m * (c - 1.0L)) * sh * sh;
+    ld p = 1.0L;
+    for (int a = 0; a < 5; ++a) {
+      S[a] += e * p;
+      p *= c;
+    }
+    if (m * (c - 1.0L) > 60.0L) break;
+  }
+}
+
+struct Pop {
+  int g;
+  int n[3];
+};
+
+std::vector<std::array<int, 3>> fs_orbit(const int b[3]) {
+  int perm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  std::set<std::array<int, 3>> s;
+  for (auto& p : perm)
+    for (int sg = 0; sg < 8; ++sg) {
+      std::array<int, 3> v;
+      for (int a = 0; a < 3; ++a) v[a] = ((sg >> a) & 1 ? -1 : 1) * b[p[a]];
+      s.insert(v);
+    }
+  return std::vector<std::array<int, 3>>(s.begin(), s.end());
+}
+
+struct Basis {
+  ld m, k1, k2, k3;
+  ld A, B, C, D, E, a1, c1, c0, d0;
+  explicit Basis(ld mbar) : m(mbar) {
+    k1 = besselk_ld(1, m);
+    k2 = besselk_ld(2, m);
+    k3 = besselk_ld(3, m);
+    ld den = m * k1 * k1 + 3 * k2 * k1 - m * k2 * k2;
+    A = sqrtl(m * (m + k2 * (3 * k1 - m * k2) / (k1 * k1)));
+    B = sqrtl(m * k2 / k1);
+    C = sqrtl(2 * m * m + 5 * m * k2 / k1 - 3 * k1 * (m * k1 + 3 * k2) / den + 3);
+    D = sqrtl(m * m * (m * k2 * k2 + 5 * k3 * k2 - m * k3 * k3) / (k1 * k2));
+    E = sqrtl(m * m * k3 / k1);
+    a1 = m * k2 / k1;
+    c1 = 3 / (-m * k1 / k2 + m * k2 / k1 - 3) - 3;
+    c0 = 3 * k1 * (m * k1 + 3 * k2) / den - m * m - 3;
+    d0 = m * k3 / k2;
+  }
+  // all 14 second-order polynomials of Appendix A at p = (p0, px, py, pz)
+  void eval14(const ld p[4], ld J[14]) const {
+    const ld s3 = sqrtl(3.0L);
+    ld p0 = p[0], x = p[1], y = p[2], z = p[3];
+    J[0] = 1;
+    J[1] = (p0 - a1) / A;
+    J[2] = x / B;
+    J[3] = y / B;
+    J[4] = z / B;
+    J[5] = (p0 * p0 + c1 * p0 + c0) / (s3 * C);
+    J[6] = x * (p0 - d0) / D;
+    J[7] = y * (p0 - d0) / D;
+    J[8] = z * (p0 - d0) / D;
+    J[9] = (y * y - z * z) / (2 * E);
+    J[10] = (-2 * x * x + y * y + z * z) / (2 * s3 * E);
+    J[11] = x * z / E;
+    J[12] = y * z / E;
+    J[13] = x * y / E;
+  }
+};
+
+// index of the 10 in-plane polynomials among the 14
+const int kInPlane[RLBM_NB] = {0, 1, 2, 3, 5, 6, 7, 9, 10, 13};
+
+bool solve_dense(int n, std::vector<ld> a, std::vector<ld> b, std::vector<ld>& x) {
+  // Gaussian elimination with partial pivoting, a row-major n x n
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabsl(a[r * n + c]) > fabsl(a[piv * n + c])) piv = r;
+    if (a[piv * n + c] == 0.0L) return false;
+    if (piv != c) {
+      for (int k = 0; k < n; ++k) std::swap(a[c * n + k], a[piv * n + k]);
+      std::swap(b[c], b[piv]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      ld f = a[r * n + c] / a[c * n + c];
+      for (int k = c; k < n; ++k) a[r * n + k] -= f * a[c * n + k];
+      b[r] -= f * b[c];
+    }
+  }
+  x.assign(n, 0.0L);
+  for (int r = n - 1; r >= 0; --r) {
+    ld s = b[r];
+    for (int k = r + 1; k < n; ++k) s -= a[r * n + k] * x[k];
+    x[r] = s / a[r * n + r];
+  }
+  return true;
+}
+
+struct Stencil {
+  ld m;
+  int ng;
+  std::vector<std::array<int, 3>> base;
+  std::vector<std::vector<std::array<int, 3>>> orbit;
+  std::vector<int> n2;
+  ld mu[5];
+  ld vmax;
+
+  Stencil(ld mbar, int n_groups, const int* gb) : m(mbar), ng(n_groups) {
+    int maxn2 = 0;
+    for (int g = 0; g < ng; ++g) {
+      std::array<int, 3> b = {gb[3 * g], gb[3 * g + 1], gb[3 * g + 2]};
+      base.push_back(b);
+      orbit.push_back(fs_orbit(b.data()));
+      n2.push_back(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+      maxn2 = std::max(maxn2, n2.back());
+    }
+    vmax = maxn2 > 0 ? 1.0L / sqrtl((ld)maxn2) : 1.0L;
+    ld S[5];
+    energy_integrals(m, S);
+    ld p = 1.0L;
+    for (int a = 0; a < 5; ++a) {
+      mu[a] = p * S[a] / S[0];
+      p *= m;
+    }
+  }
+
+  // the six reduced conditions; returns false if singular
+  bool weights(ld v0, std::vector<ld>& w) const {
+    if (ng != 6) return false;
+    std::vector<ld> a(36), b(6);
+    for (int g = 0; g < 6; ++g) {
+      ld gam = 1.0L / sqrtl(1.0L - v0 * v0 * n2[g]);
+      ld p0 = m * gam;
+      ld N = (ld)orbit[g].size();
+      ld pw = 1.0L;
+      for (int r = 0; r < 5; ++r) {
+        a[r * 6 + g] = N * pw;
+        pw *= p0;
+      }
+      ld iso = 0.0L;
+      for (auto& v : orbit[g]) iso += (ld)v[0] * v[0] * v[0] * v[0] - 3.0L * v[0] * v[0] * v[1] * v[1];
+      ld pm = m * gam * v0;
+      a[5 * 6 + g] = iso * pm * pm * pm * pm;
+    }
+    for (int r = 0; r < 5; ++r) b[r] = mu[r];
+    b[5] = 0.0L;
+    return solve_dense(6, a, b, w);
+  }
+
+  ld min_weight(ld v0) const {
+    std::vector<ld> w;
+    if (!weights(v0, w)) return -1e300L;
+    ld mn = w[0];
+    for (ld x : w) mn = std::min(mn, x);
+    return mn;
+  }
+
+  void populations(ld v0, std::vector<Pop>& pops, std::vector<std::array<ld, 4>>& mom) const {
+    pops.clear();
+    mom.clear();
+    for (int g = 0; g < ng; ++g) {
+      ld gam = 1.0L / sqrtl(1.0L - v0 * v0 * n2[g]);
+      for (auto& v : orbit[g]) {
+        pops.push_back({g, {v[0], v[1], v[2]}});
+        mom.push_back({m * gam, m * gam * v0 * v[0], m * gam * v0 * v[1], m * gam * v0 * v[2]});
+      }
+    }
+  }
+};
+
+void set_err(char* err, size_t len, const char* msg) {
+  if (err && len) snprintf(err, len, "%s", msg);
+}
+
+}  // namespace
+
+// Bessel ratio K1/K2 in long double (host reference state only)
+static ld k1k2_ld(ld z) { return besselk_ld(1, z) / besselk_ld(2, z); }
+
+int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTable* tab, char* err,
+                     size_t errlen) {
+  if (!d || !d->group_base || d->n_groups != 6 || !(d->zeta > 0) || (d->dim != 1 && d->dim != 2) ||
+      d->precision < RLBM_FP64 || d->precision > RLBM_FP16_DEV) {
+    set_err(err, errlen, "invalid stencil description (second order needs 6 groups, zeta > 0, dim 1|2)");
+    return RLBM_EINVAL;
+  }
+  for (int i = 0; i < 3 * d->n_groups; ++i)
+    if (d->group_base[i] < 0 || d->group_base[i] > 64) {
+      set_err(err, errlen, "group base components must be in [0, 64]");
+      return RLBM_EINVAL;
+    }
+  Stencil st((ld)d->zeta, d->n_groups, d->group_base);
+  for (int g = 0; g < 6; ++g)
+    for (int h = g + 1; h < 6; ++h)
+      if (st.orbit[g] == st.orbit[h]) {
+        set_err(err, errlen, "repeated velocity group");
+        return RLBM_EINVAL;
+      }
+
+  ld v0 = d->v0;
+  ld wlo = 0, whi = 0;
+  if (!(v0 > 0)) {
+    // search the interval of all-positive weights: grid, zoom on max min_k w_k, bisect edges
+    ld lo = d->v0_lo > 0 ? (ld)d->v0_lo : 1e-6L;
+    ld hi = d->v0_hi > 0 ? std::min((ld)d->v0_hi, st.vmax * (1 - 1e-12L)) : st.vmax * (1 - 1e-12L);
+    if (!(hi > lo)) {
+      set_err(err, errlen, "empty v0 search interval");
+      return RLBM_EINVAL;
+    }
+    const int G = 400;
+    ld a = lo, b = hi, best = lo, bestv = -1e300L;
+    for (int zoom = 0; zoom < 14 && bestv <= 0; ++zoom) {
+      ld step = (b - a) / G;
+      for (int i = 0; i <= G; ++i) {
+        ld v = a + step * i;
+        ld mw = st.min_weight(v);
+        if (mw > bestv) {
+          bestv = mw;
+          best = v;
+        }
+      }
+      a = std::max(best - 2 * step, lo);
+      b = std::min(best + 2 * step, hi);
+    }
+    if (!(bestv > 0)) {
+      set_err(err, errlen, "no v0 with all weights positive in the search interval");
+      return RLBM_ENOSTENCIL;
+    }
+    ld step = (b - a) / G;
+    ld l_in = best, r_in = best;
+    while (l_in - step > lo && st.min_weight(l_in - step) > 0) l_in -= step;
+    while (r_in + step < hi && st.min_weight(r_in + step) > 0) r_in += step;
+    ld l_out = std::max(l_in - step, lo), r_out = std::min(r_in + step, hi);
+    for (int it = 0; it < 100; ++it) {
+      ld mid = 0.5L * (l_in + l_out);
+      if (st.min_weight(mid) > 0) l_in = mid; else l_out = mid;
+      mid = 0.5L * (r_in + r_out);
+      if (st.min_weight(mid) > 0) r_in = mid; else r_out = mid;
+    }
+    wlo = l_in;
+    whi = r_in;
+    v0 = 0.5L * (wlo + whi);
+  }
+  if (!(v0 < st.vmax)) {
+    set_err(err, errlen, "v0 too large: a group would move faster than light");
+    return RLBM_EINVAL;
+  }
+  std::vector<ld> w;
+  if (!st.weights(v0, w)) {
+    set_err(err, errlen, "singular quadrature system for this group set");
+    return RLBM_ENOSTENCIL;
+  }
+  for (ld x : w)
+    if (!(x > 0)) {
+      set_err(err, errlen, "quadrature weights not all positive at this v0");
+      return RLBM_ENOSTENCIL;
+    }
+
+  // populations, orthonormality check over all 14 x 14 pairs
+  Basis B((ld)d->zeta);
+  std::vector<Pop> pops;
+  std::vector<std::array<ld, 4>> mom;
+  st.populations(v0, pops, mom);
+  ld G[14][14] = {};
+  std::vector<std::array<ld, 14>> Jall(pops.size());
+  for (size_t i = 0; i < pops.size(); ++i) {
+    B.eval14(mom[i].data(), Jall[i].data());
+    ld wi = w[pops[i].g];
+    for (int l = 0; l < 14; ++l)
+      for (int k = 0; k < 14; ++k) G[l][k] += wi * Jall[i][l] * Jall[i][k];
+  }
+  ld res = 0;
+  for (int l = 0; l < 14; ++l)
+    for (int k = 0; k < 14; ++k) res = std::max(res, fabsl(G[l][k] - (l == k ? 1.0L : 0.0L)));
+  if (!(res < 1e-10L)) {
+    set_err(err, errlen, "orthonormality conditions not satisfied by this group set");
+    return RLBM_ENOSTENCIL;
+  }
+
+  // classes: (group, nx, ny) in 2D, (group, nx) in 1D
+  std::map<std::tuple<int, int, int>, int> key2class;
+  std::vector<std::vector<int>> members;
+  for (size_t i = 0; i < pops.size(); ++i) {
+    auto key = std::make_tuple(pops[i].g, pops[i].n[0], d->dim == 2 ? pops[i].n[1] : 0);
+    auto it = key2class.find(key);
+    if (it == key2class.end()) {
+      key2class[key] = (int)members.size();
+      members.push_back({(int)i});
+    } else {
+      members[it->second].push_back((int)i);
+    }
+  }
+  int Q = (int)members.size();
+  if (Q > RLBM_QMAX) {
+    set_err(err, errlen, "stencil has more population classes than the library supports");
+    return RLBM_EINVAL;
+  }
+  int max_shift = 0;
+  for (auto& p : pops) max_shift = std::max(max_shift, std::max(abs(p.n[0]), d->dim == 2 ? abs(p.n[1]) : 0));
+
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->q3 = (int)pops.size();
+    info->q = Q;
+    info->v0 = (double)v0;
+    info->v0_lo = (double)wlo;
+    info->v0_hi = (double)whi;
+    for (int g = 0; g < 6; ++g) info->weights[g] = (double)w[g];
+    info->ortho_residual = (double)res;
+    info->max_shift = max_shift;
+  }
+  if (!tab) return RLBM_OK;
+
+  memset(tab, 0, sizeof(*tab));
+  RlbmConsts& c = tab->c;
+  c.Q = Q;
+  c.dim = d->dim;
+  c.precision = d->precision;
+  c.max_shift = max_shift;
+  c.zeta = d->zeta;
+  c.v0 = (double)v0;
+  c.a1 = (double)B.a1;
+  c.invA = (double)(1.0L / B.A);
+  c.invB = (double)(1.0L / B.B);
+  c.c1 = (double)B.c1;
+  c.c0 = (double)B.c0;
+  c.inv_s3C = (double)(1.0L / (sqrtl(3.0L) * B.C));
+  c.d0 = (double)B.d0;
+  c.invD = (double)(1.0L / B.D);
+  c.invE = (double)(1.0L / B.E);
+
+  std::vector<std::array<ld, RLBM_NB>> Mld(Q);
+  std::vector<std::array<ld, 3>> pj(Q);
+  for (int j = 0; j < Q; ++j) {
+    const Pop& p0 = pops[members[j][0]];
+    tab->nx[j] = p0.n[0];
+    tab->ny[j] = d->dim == 2 ? p0.n[1] : 0;
+    const auto& m0 = mom[members[j][0]];
+    pj[j] = {m0[0], m0[1], d->dim == 2 ? m0[2] : 0.0L};
+    for (int k = 0; k < RLBM_NB; ++k) {
+      ld s = 0;
+      for (int i : members[j]) s += w[pops[i].g] * Jall[i][kInPlane[k]];
+      Mld[j][k] = s;
+    }
+  }
+
+  // deviation reference: f^ref_j = n_ref sum_k b_k(rest, T_ref) M_jk
+  ld nref = d->n_ref > 0 ? d->n_ref : 1.0L;
+  ld Tref = d->T_ref > 0 ? d->T_ref : 1.0L;
+  c.n_ref = (double)nref;
+  c.T_ref = (double)Tref;
+  ld zr = (ld)d->zeta / Tref;
+  ld R = k1k2_ld(zr);
+  ld b[RLBM_NB] = {};
+  b[0] = R / (ld)d->zeta;
+  b[1] = (1.0L - B.a1 * b[0]) / B.A;
+  ld q = (ld)d->zeta * R + 4.0L * Tref;  // mbar K3(z)/K2(z)
+  b[4] = (q - Tref + B.c1 + B.c0 * b[0]) / (sqrtl(3.0L) * B.C);
+  for (int k = 0; k < RLBM_NB; ++k) c.nb_ref[k] = (double)(nref * b[k]);
+  ld refm[9] = {};
+  for (int j = 0; j < Q; ++j) {
+    ld fr = 0;
+    for (int k = 0; k < RLBM_NB; ++k) fr += nref * b[k] * Mld[j][k];
+    ld p0 = pj[j][0], px = pj[j][1], py = pj[j][2];
+    ld v[9] = {p0, px, py, p0 * p0, p0 * px, p0 * py, px * px, px * py, py * py};
+    for (int a = 0; a < 9; ++a) refm[a] += fr * v[a];
+    tab->scale[j] = (float)fr;
+    tab->inv_scale[j] = (float)(1.0L / fr);
+  }
+  for (int a = 0; a < 9; ++a) c.ref_mom[a] = (double)refm[a];
+  for (int j = 0; j < Q; ++j) {
+    tab->dnx[j] = tab->nx[j];
+    tab->dny[j] = tab->ny[j];
+    tab->fnx[j] = (float)tab->nx[j];
+    tab->fny[j] = (float)tab->ny[j];
+    tab->p0[j] = (double)pj[j][0];
+    tab->px[j] = (double)pj[j][1];
+    tab->py[j] = (double)pj[j][2];
+    tab->fp0[j] = (float)pj[j][0];
+    tab->fpx[j] = (float)pj[j][1];
+    tab->fpy[j] = (float)pj[j][2];
+    for (int k = 0; k < RLBM_NB; ++k) {
+      tab->M[k][j] = (double)Mld[j][k];
+      tab->Mf[k][j] = (float)Mld[j][k];
+    }
+  }
+  return RLBM_OK;
+}
+
+static thread_local char g_err[512];
+
+extern "C" int rlbm_solve_stencil(const rlbm_stencil_desc* desc, rlbm_stencil_info* info) {
+  return rlbm_build_table(desc, info, nullptr, g_err, sizeof(g_err));
+}
+
+extern "C" int rlbm_class_table(const rlbm_stencil_desc* desc, int cap, int* disp, double* mom, double* M) {
+  std::unique_ptr<RlbmTable> holder(new RlbmTable);
+  RlbmTable& tab = *holder;
+  rlbm_stencil_info info;
+  int rc = rlbm_build_table(desc, &info, &tab, g_err, sizeof(g_err));
+  if (rc) return rc;
+  if (cap < info.q || !disp || !mom || !M) {
+    snprintf(g_err, sizeof(g_err), "class table capacity %d < %d", cap, info.q);
+    return RLBM_EINVAL;
+  }
+  for (int j = 0; j < info.q; ++j) {
+    disp[2 * j] = tab.nx[j];
+    disp[2 * j + 1] = tab.ny[j];
+    mom[3 * j] = tab.p0[j];
+    mom[3 * j + 1] = tab.px[j];
+    mom[3 * j + 2] = tab.py[j];
+    for (int k = 0; k < RLBM_NB; ++k) M[RLBM_NB * j + k] = tab.M[k][j];
+  }
+  return RLBM_OK;
+}
+
+const char* rlbm_global_error() { return g_err; }
+void rlbm_set_global_error(const char* msg) { snprintf(g_err, sizeof(g_err), "%s", msg); }

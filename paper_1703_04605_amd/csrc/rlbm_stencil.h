@@ -1,0 +1,13 @@
+// Host-side stencil construction shared by the library's entry points.
+#pragma once
+#include <stddef.h>
+
+#include "../../include/rlbm.h"
+#include "rlbm_tables.h"
+
+// Builds the quadrature and the class table (tab may be NULL); err receives a
+// message on failure.  Returns RLBM_OK or a negative RLBM_E* code.
+int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTable* tab, char* err,
+                     size_t errlen);
+const char* rlbm_global_error();
+void rlbm_set_global_error(const char* msg);

@@ -1,0 +1,244 @@
+"""Thin ctypes binding of librlbm.so (the C ABI declared in include/rlbm.h).
+
+Argument marshalling only: every step of the relativistic lattice Boltzmann
+time step runs in the library's HIP kernels.  PyTorch provides device memory
+(population and field buffers) and the HIP stream.  If the library is not
+built, loading fails loudly; there is no fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librlbm.so")
+
+RLBM_OK = 0
+RLBM_EINVAL = -1
+RLBM_ENOSTENCIL = -2
+RLBM_EHIP = -3
+RLBM_ENUMERIC = -4
+RLBM_ESTATE = -5
+
+PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2}
+BC = {"periodic": 0, "outflow": 1}
+TAU_CONST, TAU_ETA_OVER_S = 0, 1
+ELEM_DTYPE = {"fp64": "float64", "fp32": "float32", "fp16": "float16"}
+
+H_NAN, H_LANDAU, H_SUPERLUMINAL, H_RANGE, H_EOS = 1, 2, 4, 8, 16
+
+EXPORTS = ["rlbm_init_stencil", "rlbm_solve_stencil", "rlbm_class_table", "rlbm_destroy",
+           "rlbm_population_bytes", "rlbm_init_fields", "rlbm_step", "rlbm_moments",
+           "rlbm_get_health", "rlbm_step_count", "rlbm_save_state", "rlbm_load_state",
+           "rlbm_last_error"]
+
+
+class RlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"rlbm error {code}: {msg}")
+        self.code = code
+
+
+class StencilDesc(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n_groups", ctypes.c_int),
+                ("group_base", ctypes.POINTER(ctypes.c_int)), ("zeta", ctypes.c_double),
+                ("v0", ctypes.c_double), ("v0_lo", ctypes.c_double), ("v0_hi", ctypes.c_double),
+                ("precision", ctypes.c_int), ("n_ref", ctypes.c_double), ("T_ref", ctypes.c_double)]
+
+
+class StencilInfo(ctypes.Structure):
+    _fields_ = [("q3", ctypes.c_int), ("q", ctypes.c_int), ("v0", ctypes.c_double),
+                ("v0_lo", ctypes.c_double), ("v0_hi", ctypes.c_double),
+                ("weights", ctypes.c_double * 16), ("ortho_residual", ctypes.c_double),
+                ("max_shift", ctypes.c_int)]
+
+
+class LatticeDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
+                ("tau_mode", ctypes.c_int), ("tau", ctypes.c_double), ("eta_over_s", ctypes.c_double),
+                ("T_R_GeV", ctypes.c_double), ("n_unit_fm3", ctypes.c_double), ("dx_fm", ctypes.c_double),
+                ("landau_tol", ctypes.c_double), ("landau_maxit", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads librlbm.so (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() (no CPU fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, cd, ci = ctypes.c_void_p, ctypes.c_double, ctypes.c_int
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.rlbm_init_stencil.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(StencilDesc), ctypes.POINTER(StencilInfo)]
+    L.rlbm_solve_stencil.argtypes = [ctypes.POINTER(StencilDesc), ctypes.POINTER(StencilInfo)]
+    L.rlbm_class_table.argtypes = [ctypes.POINTER(StencilDesc), ci, ctypes.POINTER(ctypes.c_int), dp, dp]
+    L.rlbm_destroy.argtypes = [vp]
+    L.rlbm_population_bytes.argtypes = [vp, ci, ci]
+    L.rlbm_population_bytes.restype = ctypes.c_size_t
+    L.rlbm_init_fields.argtypes = [vp, ctypes.POINTER(LatticeDesc), vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.rlbm_step.argtypes = [vp, ci, vp]
+    L.rlbm_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.rlbm_get_health.argtypes = [vp, ctypes.POINTER(ctypes.c_uint), ctypes.POINTER(ctypes.c_ulonglong),
+                                  ctypes.POINTER(ctypes.c_uint), ci, vp]
+    L.rlbm_step_count.argtypes = [vp]
+    L.rlbm_step_count.restype = ctypes.c_longlong
+    L.rlbm_save_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_longlong),
+                                  ctypes.POINTER(ctypes.c_int), vp]
+    L.rlbm_load_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_longlong, ci, vp]
+    L.rlbm_last_error.argtypes = [vp]
+    L.rlbm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(rc, ctx=None):
+    if rc != RLBM_OK:
+        msg = lib().rlbm_last_error(ctx)
+        raise RlbmError(rc, msg.decode() if msg else "")
+
+
+def make_desc(bases, zeta, v0=0.0, dim=2, precision="fp64", n_ref=1.0, T_ref=1.0, v0_lo=0.0, v0_hi=0.0):
+    flat = [int(c) for b in bases for c in b]
+    arr = (ctypes.c_int * len(flat))(*flat)
+    d = StencilDesc(dim, len(bases), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int)), float(zeta), float(v0),
+                    float(v0_lo), float(v0_hi), PRECISION[precision], float(n_ref), float(T_ref))
+    d._keep = arr
+    return d
+
+
+def info_dict(info):
+    return {"q3": info.q3, "q": info.q, "v0": info.v0, "v0_lo": info.v0_lo, "v0_hi": info.v0_hi,
+            "weights": [info.weights[i] for i in range(6)], "ortho_residual": info.ortho_residual,
+            "max_shift": info.max_shift}
+
+
+def solve_stencil(bases, zeta, v0=0.0, dim=2, v0_lo=0.0, v0_hi=0.0):
+    """Host-only stencil construction (no GPU): dict of the stencil info."""
+    d = make_desc(bases, zeta, v0, dim, "fp64", v0_lo=v0_lo, v0_hi=v0_hi)
+    info = StencilInfo()
+    _check(lib().rlbm_solve_stencil(ctypes.byref(d), ctypes.byref(info)))
+    return info_dict(info)
+
+
+def class_table(bases, zeta, v0, dim=2):
+    """Host-only population-class table: (disp [q,2], mom [q,3], M [q,10]) as lists."""
+    import numpy as np
+    d = make_desc(bases, zeta, v0, dim)
+    cap = 160
+    disp = (ctypes.c_int * (2 * cap))()
+    mom = (ctypes.c_double * (3 * cap))()
+    M = (ctypes.c_double * (10 * cap))()
+    _check(lib().rlbm_class_table(ctypes.byref(d), cap, disp, mom, M))
+    q = solve_stencil(bases, zeta, v0, dim)["q"]
+    return (np.array(disp[:2 * q]).reshape(q, 2), np.array(mom[:3 * q]).reshape(q, 3),
+            np.array(M[:10 * q]).reshape(q, 10))
+
+
+class Solver:
+    """One lattice on the current CUDA (HIP) device.
+
+    bases: group base vectors; zeta = m/T_R; v0 (<= 0: search the positive
+    window); precision 'fp64' | 'fp32' | 'fp16' (deviation storage)."""
+
+    def __init__(self, bases, zeta, v0, dim=2, precision="fp64", n_ref=1.0, T_ref=1.0, v0_lo=0.0, v0_hi=0.0):
+        import torch
+        self.torch = torch
+        self.precision = precision
+        self.dim = dim
+        self._desc = make_desc(bases, zeta, v0, dim, precision, n_ref, T_ref, v0_lo, v0_hi)
+        info = StencilInfo()
+        ctx = ctypes.c_void_p()
+        _check(lib().rlbm_init_stencil(ctypes.byref(ctx), ctypes.byref(self._desc), ctypes.byref(info)))
+        self.ctx = ctx
+        self.info = info_dict(info)
+        self.nx = self.ny = None
+        self.pop = None
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                lib().rlbm_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def population_bytes(self, nx, ny):
+        return lib().rlbm_population_bytes(self.ctx, nx, ny)
+
+    def init_fields(self, n, T, ux, uy, bc=("periodic", "periodic"), tau=1.0, landau_tol=0.0, landau_maxit=0):
+        """n, T, ux, uy: CUDA float64 tensors [ny, nx].  tau: float, or dict with
+        eta_over_s, T_R_GeV, n_unit_fm3, dx_fm for the eta/s rule."""
+        torch = self.torch
+        ny, nx = n.shape
+        for a in (n, T, ux, uy):
+            assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous() and tuple(a.shape) == (ny, nx)
+        if isinstance(tau, dict):
+            lat = LatticeDesc(nx, ny, BC[bc[0]], BC[bc[1]], TAU_ETA_OVER_S, 0.0, tau["eta_over_s"],
+                              tau["T_R_GeV"], tau["n_unit_fm3"], tau["dx_fm"], landau_tol, landau_maxit)
+        else:
+            lat = LatticeDesc(nx, ny, BC[bc[0]], BC[bc[1]], TAU_CONST, float(tau), 0, 0, 0, 0,
+                              landau_tol, landau_maxit)
+        nbytes = self.population_bytes(nx, ny)
+        self.pop = [torch.empty(nbytes, dtype=torch.uint8, device=n.device) for _ in range(2)]
+        self._fields = (n, T, ux, uy)
+        _check(lib().rlbm_init_fields(self.ctx, ctypes.byref(lat), n.data_ptr(), T.data_ptr(), ux.data_ptr(),
+                                      uy.data_ptr(), self.pop[0].data_ptr(), self.pop[1].data_ptr(), nbytes,
+                                      self._stream()), self.ctx)
+        self.nx, self.ny = nx, ny
+
+    def step(self, nsteps=1):
+        _check(lib().rlbm_step(self.ctx, int(nsteps), self._stream()), self.ctx)
+
+    def moments(self, raw=False):
+        """Fields of the current pre-collision state as CUDA float64 tensors."""
+        torch = self.torch
+        dev = self.pop[0].device
+        out = {k: torch.empty((self.ny, self.nx), dtype=torch.float64, device=dev)
+               for k in ("n", "eps", "T", "P", "ux", "uy")}
+        raw9 = torch.empty((9, self.ny, self.nx), dtype=torch.float64, device=dev) if raw else None
+        _check(lib().rlbm_moments(self.ctx, out["n"].data_ptr(), out["eps"].data_ptr(), out["T"].data_ptr(),
+                                  out["P"].data_ptr(), out["ux"].data_ptr(), out["uy"].data_ptr(),
+                                  raw9.data_ptr() if raw else None, self._stream()), self.ctx)
+        if raw:
+            out["raw9"] = raw9
+        return out
+
+    def health(self, reset=False):
+        f = ctypes.c_uint()
+        s = ctypes.c_ulonglong()
+        m = ctypes.c_uint()
+        rc = lib().rlbm_get_health(self.ctx, ctypes.byref(f), ctypes.byref(s), ctypes.byref(m), int(reset),
+                                   self._stream())
+        if rc not in (RLBM_OK, RLBM_ENUMERIC):
+            _check(rc, self.ctx)
+        return {"flags": f.value, "iter_sum": s.value, "iter_max": m.value, "fatal": rc == RLBM_ENUMERIC}
+
+    def step_count(self):
+        return lib().rlbm_step_count(self.ctx)
+
+    def save_state(self):
+        torch = self.torch
+        buf = torch.empty_like(self.pop[0])
+        step = ctypes.c_longlong()
+        flag = ctypes.c_int()
+        _check(lib().rlbm_save_state(self.ctx, buf.data_ptr(), buf.numel(), ctypes.byref(step), ctypes.byref(flag),
+                                     self._stream()), self.ctx)
+        return buf, step.value, flag.value
+
+    def load_state(self, buf, step, flag):
+        _check(lib().rlbm_load_state(self.ctx, buf.data_ptr(), buf.numel(), int(step), int(flag), self._stream()),
+               self.ctx)
+
+    def populations(self):
+        """Current state buffer viewed as [q, plane] in storage dtype (layout
+        flag tells whether it is the unstreamed initial state)."""
+        import numpy as np
+        torch = self.torch
+        dt = {"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.float16}[self.precision]
+        buf = self.pop[0] if (self.step_count() % 2 == 0) else self.pop[1]
+        return buf.view(dt).view(self.info["q"], -1)

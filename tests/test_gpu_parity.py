@@ -1,0 +1,150 @@
+"""Parity of the HIP library with the FP64 oracle (GPU).  Every run uses the
+seeded generators of workloads.py on both sides; fields are compared element by
+element with the per-field error max|F_gpu - F_ref| / max|F_ref|."""
+import numpy as np
+import pytest
+
+import workloads
+from tests.helpers import gpu_run, oracle_run, field_errors, to_dev, FIELDS
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1703_04605_amd import rlbm
+    rlbm.lib()
+
+
+@pytest.mark.parametrize("name", ["zeta5", "zeta1", "zeta036"])
+def test_init_recovers_fields(name):
+    """f(x, 0) = f^eq(n, T, u): the moments, Landau frame and EOS of the initial
+    state return the input fields."""
+    st = workloads.STENCILS[name]
+    fields = workloads.random_smooth(300, 5, seed=1)
+    out, _ = gpu_run(st, fields, 0, checkpoints=[0])
+    got = out[0]
+    for k, ref in zip(("n", "T", "ux", "uy"), fields):
+        assert np.abs(got[k] - ref).max() < 1e-13 * max(1, np.abs(ref).max()), k
+
+
+@pytest.mark.parametrize("name", ["zeta5", "zeta1", "zeta036"])
+def test_fp64_periodic_vs_full_stencil(name):
+    """2D periodic box, 300 x 7 (two 256-site blocks with a ragged tail), 6 steps:
+    the GPU's merged classes against the oracle's full 3D stencil."""
+    st = workloads.STENCILS[name]
+    fields = workloads.random_smooth(300, 7, seed=2)
+    g, _ = gpu_run(st, fields, 6, tau=0.9)
+    r = oracle_run(st, fields, 6, mode="full", tau=0.9)
+    errs = field_errors(g[6], r[6])
+    assert max(errs.values()) < FP64_TOL, errs
+
+
+def test_fp64_outflow_2d():
+    st = workloads.STENCILS["zeta1"]
+    fields = workloads.random_smooth(40, 30, seed=4)
+    bc = ("outflow", "outflow")
+    g, _ = gpu_run(st, fields, 8, bc=bc, tau=1.1)
+    r = oracle_run(st, fields, 8, bc=bc, tau=1.1)
+    errs = field_errors(g[8], r[8])
+    assert max(errs.values()) < FP64_TOL, errs
+
+
+def test_riemann_800x1_fp64_eta_over_s():
+    """The quasi-1D shock tube (800 x 1, zeta = 1, eta/s = 0.1, outflow), the
+    full 500 steps, fields checked every 100 steps."""
+    st = workloads.STENCILS["zeta1"]
+    fields, tau = workloads.riemann_1d(800)
+    cps = [100, 200, 300, 400, 500]
+    bc = ("outflow", "periodic")
+    g, s = gpu_run(st, fields, 500, dim=1, bc=bc, tau=tau, checkpoints=cps)
+    r = oracle_run(st, fields, 500, dim=1, bc=bc, tau=tau, checkpoints=cps)
+    for c in cps:
+        errs = field_errors(g[c], r[c], ("n", "eps", "T", "P", "ux"))
+        assert max(errs.values()) < FP64_TOL, (c, errs)
+    assert s.health()["flags"] == 0
+
+
+def test_1d_matches_2d_on_gpu():
+    """Fig. 7: the 2D run of the Riemann problem equals the 1D run."""
+    st = workloads.STENCILS["zeta5"]
+    (n, T, ux, uy), tau = workloads.riemann_1d(64)
+    ny = 4
+    g1, _ = gpu_run(st, (n, T, ux, uy), 20, dim=1, bc=("outflow", "periodic"), tau=tau)
+    g2, _ = gpu_run(st, tuple(np.repeat(a, ny, axis=0) for a in (n, T, ux, uy)), 20, dim=2,
+                    bc=("outflow", "periodic"), tau=tau)
+    assert np.isfinite(g1[20]["n"]).all()
+    for k in ("n", "T", "ux"):
+        assert np.abs(g2[20][k] - g1[20][k]).max() < 1e-13, k
+
+
+def test_conservation_fp64():
+    st = workloads.STENCILS["zeta1"]
+    fields = workloads.taylor_green(64, 48, seed=5)
+    g, _ = gpu_run(st, fields, 100, checkpoints=[0, 100])
+    t0 = g[0]["raw9"].sum(axis=(1, 2))
+    t1 = g[100]["raw9"].sum(axis=(1, 2))
+    for k in (0, 3, 4, 5):
+        assert abs(t1[k] - t0[k]) < 1e-12 * abs(t0[3]), k
+
+
+def test_uniform_state_fixed_point():
+    st = workloads.STENCILS["zeta5"]
+    ones = np.ones((9, 260))
+    g, _ = gpu_run(st, (1.3 * ones, 0.8 * ones, 0.3 * ones, -0.2 * ones), 20, checkpoints=[0, 20])
+    for k in ("n", "T", "ux", "uy"):
+        assert np.abs(g[20][k] - g[0][k]).max() < 1e-13, k
+
+
+@pytest.mark.parametrize("name", ["zeta1", "zeta5"])
+def test_fp32_deviation_vs_oracle(name):
+    st = workloads.STENCILS[name]
+    fields = workloads.taylor_green(96, 64, seed=6)
+    cps = [1, 20]
+    g, _ = gpu_run(st, fields, 20, precision="fp32", tau=1.0, checkpoints=cps)
+    r = oracle_run(st, fields, 20, tau=1.0, checkpoints=cps)
+    for c in cps:
+        errs = field_errors(g[c], r[c])
+        assert max(errs.values()) < FP32_TOL, (c, errs)
+
+
+def test_fp16_deviation_vs_oracle():
+    st = workloads.STENCILS["zeta1"]
+    fields = workloads.kelvin_helmholtz(64, 64, seed=7)
+    g, _ = gpu_run(st, fields, 20, precision="fp16", tau=1.0)
+    r = oracle_run(st, fields, 20, tau=1.0)
+    errs = field_errors(g[20], r[20], ("n", "eps", "T", "P"))
+    speed = np.hypot(r[20]["ux"], r[20]["uy"]).max()
+    for k in ("ux", "uy"):
+        errs[k] = float(np.abs(g[20][k] - r[20][k]).max() / speed)
+    print("fp16 per-field error after 20 steps (velocities relative to max |u|):", errs)
+    assert max(errs.values()) < 1e-3, errs
+
+
+def test_health_flags_from_host_forced_cap():
+    """landau_maxit = 1 forces the iteration cap from the host: the flag is
+    raised, nothing fatal."""
+    st = workloads.STENCILS["zeta5"]
+    fields = workloads.random_smooth(64, 8, seed=8)
+    _, s = gpu_run(st, fields, 1, landau_maxit=1)
+    h = s.health()
+    assert h["flags"] & 2 and not h["fatal"]
+
+
+def test_checkpoint_resume_bitwise():
+    st = workloads.STENCILS["zeta1"]
+    fields = workloads.taylor_green(80, 40, seed=9)
+    _, s = gpu_run(st, fields, 7, precision="fp32")
+    buf, step, flag = s.save_state()
+    s.step(5)
+    ref = s.moments()["n"].cpu().numpy()
+    s.load_state(buf, step, flag)
+    assert s.step_count() == 7
+    s.step(5)
+    assert np.array_equal(s.moments()["n"].cpu().numpy(), ref)

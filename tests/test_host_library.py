@@ -1,0 +1,93 @@
+"""CPU tests of the C ABI library: it loads, exports every symbol the header
+declares, and its host-side stencil construction (long double, reduced
+six-condition system) agrees with the oracle (mpmath, all 105 pair conditions)."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads
+from paper_1703_04605_amd import rlbm
+from oracle import quadrature as quad, lattice as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PINS = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_pins.json")))
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "rlbm.h")).read()
+    return sorted(set(re.findall(r"\b(rlbm_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L_ = rlbm.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 13
+    for s in syms:
+        assert hasattr(L_, s), s
+    assert set(rlbm.EXPORTS) <= set(syms)
+
+
+def test_printed_weights_from_library():
+    q = PINS["quadrature_m5_G1_G6"]
+    info = rlbm.solve_stencil(workloads.STENCILS["zeta5"]["bases"], 5.0, 0.398)
+    for w, p in zip(info["weights"], q["weights_truncated"]):
+        assert 0 <= w - p < 1e-10
+    assert info["q3"] == q["n_populations"] and info["ortho_residual"] < 1e-13
+
+
+def test_window_search_matches_paper():
+    q = PINS["quadrature_m5_G1_G6"]
+    info = rlbm.solve_stencil(workloads.STENCILS["zeta5"]["bases"], 5.0, 0.0, v0_lo=0.39, v0_hi=0.40)
+    assert abs(info["v0_lo"] - q["prune_w2_v0"]) < 1e-9
+    assert abs(info["v0_hi"] - q["prune_w3_v0"]) < 1e-9
+
+
+@pytest.mark.parametrize("name", list(workloads.STENCILS))
+def test_weights_match_oracle(name):
+    st = workloads.STENCILS[name]
+    info = rlbm.solve_stencil(st["bases"], st["zeta"], st["v0"])
+    w, res = quad.weights(st["bases"], st["zeta"], st["v0"])
+    for a, b in zip(info["weights"], w):
+        assert abs(a - float(b)) < 1e-13 * max(1.0, abs(float(b))) + 1e-15
+    assert info["ortho_residual"] < 1e-12 and min(info["weights"]) > 0
+
+
+@pytest.mark.parametrize("name,dim", [("zeta5", 2), ("zeta1", 2), ("zeta036", 2), ("zeta1", 1)])
+def test_class_table_matches_oracle_projection(name, dim):
+    """The library's merged population classes equal the oracle's projected set
+    (same displacement, momenta and aggregated w_i J_k(p_i))."""
+    st = workloads.STENCILS[name]
+    disp, mom, M = rlbm.class_table(st["bases"], st["zeta"], st["v0"], dim)
+    ps = L.build_stencil(st["bases"], st["zeta"], st["v0"], mode="projected", dim=dim)
+    assert ps.Q == disp.shape[0]
+    # oracle column order: 0,1_0,1_x,1_y,1_z,2_00,2_0x,2_0y,2_0z,2_xx,2_yy,2_xz,2_yz,2_xy
+    cols = [0, 1, 2, 3, 5, 6, 7, 9, 10, 13]
+    key = lambda d, p0: (int(d[0]), int(d[1]), round(float(p0), 9))
+    ours = {key(disp[j], mom[j, 0]): (mom[j], M[j]) for j in range(ps.Q)}
+    for j in range(ps.Q):
+        k = key(ps.disp[j], ps.p[j, 0])
+        assert k in ours
+        m_ours, M_ours = ours[k]
+        p = np.zeros(3)
+        p[:ps.d] = ps.p[j]
+        assert np.abs(m_ours - p).max() < 1e-13 * max(1, np.abs(p).max())
+        assert np.abs(M_ours - ps.M[j, cols]).max() < 1e-13 * max(1.0, np.abs(ps.M[j]).max())
+
+
+def test_error_codes():
+    b = workloads.STENCILS["zeta5"]["bases"]
+    with pytest.raises(rlbm.RlbmError) as e:
+        rlbm.solve_stencil(b[:5], 5.0, 0.398)          # five groups: not second order
+    assert e.value.code == rlbm.RLBM_EINVAL
+    with pytest.raises(rlbm.RlbmError) as e:
+        rlbm.solve_stencil(b, 5.0, 0.30)               # weights not all positive
+    assert e.value.code == rlbm.RLBM_ENOSTENCIL
+    with pytest.raises(rlbm.RlbmError) as e:
+        rlbm.solve_stencil(b, 5.0, 0.5)                # G6 faster than light
+    assert e.value.code == rlbm.RLBM_EINVAL
+    with pytest.raises(rlbm.RlbmError) as e:           # mbar = 0.1: no positive window for this set
+        rlbm.solve_stencil(workloads.STENCILS["zeta036"]["bases"], 0.1, 0.0)
+    assert e.value.code == rlbm.RLBM_ENOSTENCIL

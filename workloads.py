@@ -1,0 +1,98 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle
+runs: stencil choices (group base vectors, zeta = m/T_R, v0) and initial
+fields.  This module holds no arithmetic of the method itself.
+
+Stencils (group bases from Appendix C of arXiv:1703.04605):
+  zeta5   G1..G6 at mbar = 5, v0 = 0.398: the paper's worked example (Sec. III.D)
+  zeta1   G1,G5,G11,G13,G17,G21 at mbar = 1 (no stencil for mbar = 1 is printed;
+          v0 at the midpoint of its positive-weight window)
+  zeta036 G1,G14,G49,G51,G60,G70 at mbar = 0.36: the paper's 133-population
+          stencil of its BAMPS comparison (Fig. 6), v0 at the window midpoint
+  zeta10  G1..G6 at mbar = 10, v0 at the window midpoint
+"""
+import numpy as np
+
+STENCILS = {
+    "zeta5": {"groups": [1, 2, 3, 4, 5, 6],
+              "bases": [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 1), (2, 0, 0), (2, 1, 0)],
+              "zeta": 5.0, "v0": 0.398},
+    "zeta1": {"groups": [1, 5, 11, 13, 17, 21],
+              "bases": [(0, 0, 0), (2, 0, 0), (3, 0, 0), (3, 2, 0), (3, 2, 2), (4, 0, 0)],
+              "zeta": 1.0, "v0": 0.2403918860},
+    "zeta036": {"groups": [1, 14, 49, 51, 60, 70],
+                "bases": [(0, 0, 0), (3, 3, 0), (5, 4, 2), (5, 3, 3), (6, 3, 0), (6, 2, 2)],
+                "zeta": 0.36, "v0": 0.1488231854},
+    "zeta10": {"groups": [1, 2, 3, 4, 5, 6],
+               "bases": [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 1), (2, 0, 0), (2, 1, 0)],
+               "zeta": 10.0, "v0": 0.3752119693},
+}
+
+# The quasi-1D Riemann workload: left P = 5.43 GeV/fm^3 at T = 0.35 GeV, right
+# P = 0.339 GeV/fm^3 at T = 0.2 GeV, u = 0, eta/s = 0.1, on a 6.4 fm domain
+# (pressures, eta/s and domain as in the paper's BAMPS benchmark, Sec. IV).
+RIEMANN = {"P_left": 5.43, "T_left_GeV": 0.35, "P_right": 0.339, "T_right_GeV": 0.2, "eta_over_s": 0.1,
+           "domain_fm": 6.4}
+
+
+def riemann_1d(nx=800):
+    """Quasi-1D shock tube: left/right constant states, u = 0, interface
+    between cells nx/2 - 1 and nx/2.  T_R = the left (hottest) temperature."""
+    TR = RIEMANN["T_left_GeV"]
+    nL = RIEMANN["P_left"] / RIEMANN["T_left_GeV"]           # fm^-3
+    nR = RIEMANN["P_right"] / RIEMANN["T_right_GeV"]
+    left = np.arange(nx) < nx // 2
+    n = np.where(left, 1.0, nR / nL)[None, :]
+    T = np.where(left, 1.0, RIEMANN["T_right_GeV"] / TR)[None, :]
+    z = np.zeros((1, nx))
+    tau = {"eta_over_s": RIEMANN["eta_over_s"], "T_R_GeV": TR, "n_unit_fm3": nL,
+           "dx_fm": RIEMANN["domain_fm"] / nx}
+    return (n, T, z, z.copy()), tau
+
+
+def taylor_green(nx, ny, seed=0, umax=0.3, noise=0.01):
+    """Periodic Taylor-Green-type vortex with peak speed umax, plus 1%
+    Gaussian noise on n and T around n = T = 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(x, y)
+    ux = umax * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Y)
+    uy = -umax * np.cos(2 * np.pi * X) * np.sin(2 * np.pi * Y)
+    n = 1.0 + noise * rng.standard_normal((ny, nx))
+    T = 1.0 + noise * rng.standard_normal((ny, nx))
+    return n, T, ux, uy
+
+
+def kelvin_helmholtz(nx, ny, seed=0, beta=0.4, width=8.0, amp=0.01):
+    """Doubly periodic shear layers at y = L/4, 3L/4 with tanh profile of the
+    given width (cells), speed +-beta, and a seeded sinusoidal transverse
+    perturbation of amplitude amp; n = T = 1."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = int(rng.integers(1, 5))
+    phi = float(rng.uniform(0, 2 * np.pi))
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny) + 0.5
+    X, Y = np.meshgrid(x, y)
+    ux = beta * (np.tanh((Y - ny / 4) / width) - np.tanh((Y - 3 * ny / 4) / width) - 1.0)
+    uy = amp * np.sin(2 * np.pi * k * X / nx + phi)
+    return np.ones((ny, nx)), np.ones((ny, nx)), ux, uy
+
+
+def random_smooth(nx, ny, seed=0, umax=0.3):
+    """Random smooth periodic fields (a few Fourier modes) for parity tests."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x = np.arange(nx) / nx
+    y = np.arange(ny) / ny
+    X, Y = np.meshgrid(x, y)
+
+    def field(amp):
+        f = np.zeros((ny, nx))
+        for _ in range(3):
+            kx, ky = rng.integers(0, 3, 2)
+            f += amp * rng.uniform(-1, 1) * np.cos(2 * np.pi * (kx * X + ky * Y) + rng.uniform(0, 6.3))
+        return f
+
+    n = 1.0 + field(0.1)
+    T = 1.0 + field(0.1)
+    ux, uy = field(umax / 3), field(umax / 3)
+    return n, T, ux, uy
