@@ -45,11 +45,11 @@ def measured_traffic(precision, nx, ny):
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
-def time_path(st, fields, precision, steps, warmup, tau=1.0):
+def time_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton"):
     import torch
     from paper_1703_04605_amd import rlbm
     s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=2, precision=precision)
-    s.init_fields(*fields, tau=tau)
+    s.init_fields(*fields, tau=tau, landau=landau)
     s.step(warmup)
     s.health(reset=True)
     stream = torch.cuda.current_stream()
@@ -131,17 +131,19 @@ def main():
                               "landau_iter_mean": iters_mean, "landau_iter_max": h["iter_max"],
                               "health_flags": h["flags"]}}
     if not args.no_compare:
-        for p in ("fp64", "fp32", "fp16"):
-            if p == args.precision:
+        for key in ("fp64", "fp32", "fp16", "fp64_fixed_point", "fp32_fixed_point"):
+            p = key.split("_")[0]
+            landau = "fixed_point" if key.endswith("fixed_point") else "newton"
+            if key == args.precision:
                 continue
-            s2, ms2, _, h2 = time_path(st, fields, p, args.steps, args.warmup)
+            s2, ms2, _, h2 = time_path(st, fields, p, args.steps, args.warmup, landau=landau)
             m2 = sites * args.steps / (ms2 * 1e-3) / 1e6
             ab = 2 * q * ELEM[p] * sites / (ms2 / args.steps * 1e-3) / 1e9
             o2 = {k: v.cpu().numpy() for k, v in s2.moments().items()}
-            paths[p] = {"mlups": m2, "ms_per_step": ms2 / args.steps, "hbm_frac": ab / HBM_PEAK_GBS,
+            paths[key] = {"mlups": m2, "ms_per_step": ms2 / args.steps, "hbm_frac": ab / HBM_PEAK_GBS,
                         "landau_iter_mean": h2["iter_sum"] / (sites * args.steps),
                         "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"]}
-            if p == "fp64":
+            if key == "fp64":
                 # deviation of the headline path from the float64 GPU path (itself
                 # parity-tested against the oracle) after the full horizon
                 paths[args.precision]["max_rel_err_vs_fp64_path"] = {

@@ -131,6 +131,15 @@ int rlbm_solve_stencil(const rlbm_stencil_desc* desc, rlbm_stencil_info* info);
  */
 int rlbm_class_table(const rlbm_stencil_desc* desc, int cap, int* disp, double* mom, double* M);
 
+/*
+ * Host-only: temperatures T[i] solving e[i] = 3T + zeta K_1(zeta/T)/K_2(zeta/T)
+ * (eq. relativistic-eos, energy per particle e = eps/n, T_R = 1) from the same
+ * piecewise Chebyshev table of T(e - zeta) that the GPU kernels evaluate
+ * (quarter octaves of e - zeta, built in long double for this zeta).  n values,
+ * host arrays.  Errors: RLBM_EINVAL.
+ */
+int rlbm_eos_temperature_host(double zeta, const double* e, int n, double* T);
+
 /* Frees the context and its device tables (after synchronising its work). */
 int rlbm_destroy(rlbm_ctx* ctx);
 
@@ -147,10 +156,18 @@ typedef struct {
    * with s = 4n - n ln(n / n_eq), n_eq = 16 T^3 / (pi^2 (hbar c)^3), in
    * physical units: T = T_lat * T_R_GeV, n = n_lat * n_unit_fm3. */
   double eta_over_s, T_R_GeV, n_unit_fm3, dx_fm;
-  double landau_tol;     /* stop when |d eps| <= tol eps (0: 1e-14 for FP64,
-                            1e-10 otherwise) */
+  double landau_tol;     /* target relative accuracy of eps and u (0: 1e-14
+                            for FP64, 1e-10 otherwise) */
   int landau_maxit;      /* iteration cap (0: 200) */
+  int landau_method;     /* RLBM_LANDAU_NEWTON: Newton on the characteristic
+                            polynomial det(l I - T eta) from l = T^00, then u
+                            from the spatial rows; RLBM_LANDAU_FIXED_POINT:
+                            eps = T^00 - T^0i u_i, u_i = (T^0i - T^ij u_j)/eps
+                            from u = 0, until |d eps| <= tol eps, |d u| <= tol */
 } rlbm_lattice_desc;
+
+#define RLBM_LANDAU_NEWTON 0
+#define RLBM_LANDAU_FIXED_POINT 1
 
 /*
  * Sets f_i(x, 0) = f_i^eq(n, T, u) (eq. mj-discrete-feq with the density n

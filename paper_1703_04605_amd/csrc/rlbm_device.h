@@ -10,6 +10,12 @@
 
 namespace rlbm {
 
+// The stencil table is read-only for the whole lifetime of every kernel;
+// reading it through the constant address space lets uniform accesses become
+// scalar loads through the scalar cache.
+typedef const __attribute__((address_space(4))) RlbmTable* TabPtr;
+__device__ __forceinline__ TabPtr as_tab(const RlbmTable* p) { return (TabPtr)p; }
+
 // R(z) = K_1(z)/K_2(z), the Bessel ratio of the equation of state
 // (eq. relativistic-eos).  For z < 1.5: the ascending series of K_0 and K_1
 // (integer-order expansions with the logarithmic term, e.g. Abramowitz &
@@ -17,28 +23,36 @@ namespace rlbm {
 // expansion in t = 3/z - 1 (coefficients generated from mpmath).
 __device__ __forceinline__ double k1k2_ratio(double z) {
   if (z < RLBM_BESSEL_Z_SPLIT) {
-    const double euler_gamma = 0.57721566490153286061;
+    // term ratios 1/k^2, 1/(k(k+1)) and the digamma sums 2 H_k + 1/(k+1) - 2 gamma
+    constexpr double inv_k2[13] = {0, 1.0, 1.0 / 4, 1.0 / 9, 1.0 / 16, 1.0 / 25, 1.0 / 36, 1.0 / 49,
+                                   1.0 / 64, 1.0 / 81, 1.0 / 100, 1.0 / 121, 1.0 / 144};
+    constexpr double inv_kk1[13] = {0, 1.0 / 2, 1.0 / 6, 1.0 / 12, 1.0 / 20, 1.0 / 30, 1.0 / 42, 1.0 / 56,
+                                    1.0 / 72, 1.0 / 90, 1.0 / 110, 1.0 / 132, 1.0 / 156};
+    constexpr double euler_gamma = 0.57721566490153286061;
+    double Hk[13], D1[13];
+    Hk[0] = 0.0;
+#pragma unroll
+    for (int k = 1; k < 13; ++k) Hk[k] = Hk[k - 1] + 1.0 / (double)k;   // folded at compile time
+#pragma unroll
+    for (int k = 0; k < 13; ++k) D1[k] = 2.0 * Hk[k] + 1.0 / (double)(k + 1) - 2.0 * euler_gamma;
     const double y = 0.25 * z * z;
-    double t0 = 1.0, t1 = 1.0;     // y^k/(k!)^2, y^k/(k!(k+1)!)
-    double I0 = 1.0, I1s = 1.0;    // I0(z), 2 I1(z)/z
-    double S0 = 0.0;               // sum H_k y^k/(k!)^2
-    double S1 = 1.0 - 2.0 * euler_gamma;  // sum (2H_k + 1/(k+1) - 2 gamma) y^k/(k!(k+1)!)
-    double H = 0.0;
+    double t0 = 1.0, t1 = 1.0;           // y^k/(k!)^2, y^k/(k!(k+1)!)
+    double I0 = 1.0, I1s = 1.0;          // I0(z), 2 I1(z)/z
+    double S0 = 0.0, S1 = D1[0];         // sum H_k t0_k, sum D1_k t1_k
 #pragma unroll
     for (int k = 1; k < 13; ++k) {
-      const double kk = (double)k;
-      H += 1.0 / kk;
-      t0 *= y / (kk * kk);
-      t1 *= y / (kk * (kk + 1.0));
+      t0 *= y * inv_k2[k];
+      t1 *= y * inv_kk1[k];
       I0 += t0;
       I1s += t1;
-      S0 = fma(H, t0, S0);
-      S1 = fma(2.0 * H + 1.0 / (kk + 1.0) - 2.0 * euler_gamma, t1, S1);
+      S0 = fma(Hk[k], t0, S0);
+      S1 = fma(D1[k], t1, S1);
     }
     const double L = log(0.5 * z);
+    const double iz = 1.0 / z;
     const double K0 = S0 - (L + euler_gamma) * I0;
-    const double K1 = 1.0 / z + 0.5 * z * (L * I1s - 0.5 * S1);
-    return K1 / (K0 + 2.0 * K1 / z);
+    const double K1 = iz + 0.5 * z * (L * I1s - 0.5 * S1);
+    return K1 / fma(2.0 * iz, K1, K0);
   }
   const double t = 2.0 * RLBM_BESSEL_Z_SPLIT / z - 1.0;
   const double t2 = 2.0 * t;
@@ -79,6 +93,68 @@ __device__ __forceinline__ double eos_temperature(double e, double zeta, unsigne
   return t;
 }
 
+// Inverse EOS from the per-stencil table: T = u g(u), u = e - zeta, with g a
+// Chebyshev series on the quarter-octave of u (built on the host in long
+// double from the same equation); Newton fallback outside the tabulated range.
+__device__ __forceinline__ double eos_temperature_tab(TabPtr tb, double e, double zeta,
+                                                     unsigned& flags) {
+  const double u = e - zeta;
+  int ex;
+  const double m = frexp(u, &ex);          // u = m 2^ex, m in [1/2, 1)
+  const int o = ex - 1 - RLBM_EOS_KMIN;
+  if (!(u > 0.0) || o < 0 || o >= RLBM_EOS_NOCT) return eos_temperature(e, zeta, flags);
+  const double m2 = 2.0 * m;                // [1, 2)
+  const int piece = min((int)((m2 - 1.0) * 4.0), 3);
+  const double t = (m2 - 1.0 - 0.25 * piece) * 8.0 - 1.0;
+  const __attribute__((address_space(4))) double* c = tb->eos[o * 4 + piece];
+  const double t2 = 2.0 * t;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int j = RLBM_EOS_DEG - 1; j >= 1; --j) {
+    const double b0 = fma(t2, b1, c[j] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return u * fma(t, b1, c[0] - b2);
+}
+
+// Landau frame by Newton's method on the characteristic polynomial of the
+// mixed tensor: eps is the largest root of p(l) = det(l I - T eta), with
+//   p(l) = (l - T00)[(l + Txx)(l + Tyy) - Txy^2] + T0x^2 (l + Tyy)
+//          - 2 T0x T0y Txy + T0y^2 (l + Txx).
+// T^00 bounds eps from above and p is increasing and convex to the right of
+// its largest root, so the iterates decrease monotonically.  The velocity then
+// solves (eps delta_ij + T^ij) u_j = T^0i, the spatial rows of the eigenproblem.
+// Stops one iteration after the step falls below `thresh` (quadratic
+// convergence).  Returns the iteration count (maxit + 1 if the cap was hit).
+__device__ __forceinline__ int landau_newton(double T00, double T0x, double T0y, double Txx, double Txy,
+                                             double Tyy, double thresh, int maxit, double& eps, double& ux,
+                                             double& uy) {
+  double l = T00;
+  const double b2c2 = T0x * T0x + T0y * T0y;
+  const double bce2 = 2.0 * T0x * T0y * Txy;
+  const double e2 = Txy * Txy;
+  int it = 1;
+  bool done = false;
+  for (; it <= maxit; ++it) {
+    const double pd = l + Txx, pf = l + Tyy;
+    const double m = fma(pd, pf, -e2);
+    const double la = l - T00;
+    const double p = fma(la, m, fma(T0x * T0x, pf, fma(T0y * T0y, pd, -bce2)));
+    const double dp = fma(la, pd + pf, m + b2c2);
+    const double step = p / dp;
+    l -= step;
+    if (done) break;
+    if (fabs(step) <= thresh * l) done = true;
+  }
+  const double pd = l + Txx, pf = l + Tyy;
+  const double inv = 1.0 / fma(pd, pf, -e2);
+  ux = (T0x * pf - T0y * Txy) * inv;
+  uy = (T0y * pd - T0x * Txy) * inv;
+  eps = l;
+  return it;
+}
+
 // Landau frame (eqs. landau-lifshitz-*): eps U^a = T^{ab} U_b with
 // U = gamma (1, ux, uy), as the fixed point
 //   eps = T^00 - T^0i u_i,   u_i = (T^0i - T^ij u_j) / eps,
@@ -110,8 +186,9 @@ __device__ __forceinline__ int landau_solve(double T00, double T0x, double T0y, 
 // distribution on the 10 in-plane second-order polynomials (Appendix B; T_R = 1
 // so a_k = b_k).  From the moments int f p = U, int f p p = q U U - T eta,
 // q = mbar K_3(z)/K_2(z) = zeta R + 4T, int f = R/zeta.
-__device__ __forceinline__ void projections(const RlbmConsts& c, double T, double R, double U0, double Ux,
-                                            double Uy, double b[RLBM_NB]) {
+__device__ __forceinline__ void projections(TabPtr tb, double T, double R, double U0, double Ux, double Uy,
+                                            double b[RLBM_NB]) {
+  const auto& c = tb->c;
   const double b0 = R / c.zeta;
   const double q = fma(c.zeta, R, 4.0 * T);
   b[0] = b0;
@@ -139,16 +216,6 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   const int q = nb >> 3, r = nb & 7;
   const int xcd = b & 7, k = b >> 3;
   return xcd * q + min(xcd, r) + k;
-}
-
-__device__ __forceinline__ int wrap_or_clamp(int s, int n, int bc, int small) {
-  if (bc == RLBM_BC_PERIODIC) {
-    if (small) return ((s % n) + n) % n;
-    s += (s < 0) ? n : 0;
-    s -= (s >= n) ? n : 0;
-    return s;
-  }
-  return min(max(s, 0), n - 1);
 }
 
 }  // namespace rlbm

@@ -34,13 +34,13 @@ template <> struct Traits<RLBM_FP32_DEV> { using S = float; using A = float; };
 template <> struct Traits<RLBM_FP16_DEV> { using S = _Float16; using A = float; };
 
 template <int P>
-__device__ __forceinline__ typename Traits<P>::A to_arith(typename Traits<P>::S v, const RlbmTable* tb, int j) {
+__device__ __forceinline__ typename Traits<P>::A to_arith(typename Traits<P>::S v, TabPtr tb, int j) {
   if constexpr (P == RLBM_FP16_DEV) return (float)v * tb->scale[j];
   else return v;
 }
 
 template <int P>
-__device__ __forceinline__ typename Traits<P>::S to_store(typename Traits<P>::A v, const RlbmTable* tb, int j) {
+__device__ __forceinline__ typename Traits<P>::S to_store(typename Traits<P>::A v, TabPtr tb, int j) {
   if constexpr (P == RLBM_FP16_DEV) return (_Float16)(v * tb->inv_scale[j]);
   else return v;
 }
@@ -84,69 +84,125 @@ struct Macro {
   unsigned flags;
 };
 
-__device__ __forceinline__ Macro macroscopic(const RlbmConsts& c, double N0, double Nx, double Ny, double T00,
-                                             double T0x, double T0y, double Txx, double Txy, double Tyy,
-                                             double tol, int maxit) {
+__device__ __forceinline__ Macro macroscopic(TabPtr tb, double N0, double Nx, double Ny,
+                                             double T00, double T0x, double T0y, double Txx, double Txy,
+                                             double Tyy, double tol, int maxit, int method) {
   Macro m;
   m.flags = 0;
   m.ux = 0.0;
   m.uy = 0.0;
-  m.iters = landau_solve(T00, T0x, T0y, Txx, Txy, Tyy, tol, maxit, m.eps, m.ux, m.uy);
+  if (method == RLBM_LANDAU_NEWTON)
+    m.iters = landau_newton(T00, T0x, T0y, Txx, Txy, Tyy, 0.1 * sqrt(tol), maxit, m.eps, m.ux, m.uy);
+  else
+    m.iters = landau_solve(T00, T0x, T0y, Txx, Txy, Tyy, tol, maxit, m.eps, m.ux, m.uy);
   if (m.iters > maxit) m.flags |= RLBM_H_LANDAU;
   const double u2 = m.ux * m.ux + m.uy * m.uy;
   if (!(u2 < 1.0)) m.flags |= RLBM_H_SUPERLUMINAL;
   m.gamma = 1.0 / sqrt(1.0 - u2);
   m.n = m.gamma * (N0 - m.ux * Nx - m.uy * Ny);
   if (!(m.n > 0.0) || !(m.eps > 0.0)) m.flags |= RLBM_H_RANGE;
-  m.T = eos_temperature(m.eps / m.n, c.zeta, m.flags);
+  const double zeta = tb->c.zeta;
+  const double e = m.eps / m.n;
+  m.T = eos_temperature_tab(tb, e, zeta, m.flags);
   m.P = m.n * m.T;
-  m.R = k1k2_ratio(c.zeta / m.T);
+  // K1/K2 at z = zeta/T from the EOS itself: zeta R = e - 3T
+  m.R = (e - 3.0 * m.T) / zeta;
   if (!isfinite(m.T) || !isfinite(m.eps) || !isfinite(m.n) || !isfinite(m.R)) m.flags |= RLBM_H_NAN;
   return m;
 }
 
+// ------------------------------------------------------------------ layout
+
+// Ghost cells of one axis: bit i stands for ghost coordinate c_i = i - S
+// (i < S) or n + i - S (i >= S); it is set when the boundary rule maps c_i to
+// the owner coordinate x (periodic: c mod n; outflow: clamp to [0, n)).
+__device__ __forceinline__ unsigned ghost_mask(int x, int n, int S, int bc) {
+  unsigned m = 0;
+  for (int i = 0; i < 2 * S; ++i) {
+    const int c = i < S ? i - S : n + (i - S);
+    const int src = bc == RLBM_BC_PERIODIC ? ((c % n) + n) % n : min(max(c, 0), n - 1);
+    if (src == x) m |= 1u << i;
+  }
+  return m;
+}
+
+__device__ __forceinline__ int ghost_coord(int i, int n, int S) { return i < S ? i - S : n + (i - S); }
+
+// Writes v to every ghost copy of site (x, y) in plane q (the owner copy is
+// written by the caller).
+template <typename S>
+__device__ __forceinline__ void store_ghosts(S* __restrict__ q, const RlbmLayout& L, int x, int y, unsigned xm,
+                                             unsigned ym, S v) {
+  for (unsigned m = xm; m; m &= m - 1)
+    q[(long long)(y + L.GY) * L.W + ghost_coord(__builtin_ctz(m), L.nx, L.Sx) + L.GX] = v;
+  for (unsigned r = ym; r; r &= r - 1) {
+    const long long row = (long long)(ghost_coord(__builtin_ctz(r), L.ny, L.Sy) + L.GY) * L.W;
+    q[row + x + L.GX] = v;
+    for (unsigned m = xm; m; m &= m - 1) q[row + ghost_coord(__builtin_ctz(m), L.nx, L.Sx) + L.GX] = v;
+  }
+}
+
 // ------------------------------------------------------------------ step
 
-template <int QCAP, int P>
-__global__ void __launch_bounds__(kBlock) k_step(RlbmStepArgs a) {
+// Waves per SIMD requested from the register allocator: enough to overlap one
+// wave's arithmetic with other waves' loads, while the class values of the
+// largest stencils still fit in registers.
+constexpr int step_waves(int qn, int p) {
+  return p == RLBM_FP64 ? (qn <= 48 ? 3 : qn <= 80 ? 2 : 1) : (qn <= 48 ? 4 : qn <= 80 ? 3 : 2);
+}
+
+// One time step for a block of kBlock consecutive sites of one row, for a
+// stencil of at most QN classes.  The class loops are fully unrolled, so the
+// populations stay in registers; the pull loop is unguarded so all pulls are
+// issued back to back (classes Q <= j < QN read class 0's source and have
+// all-zero table rows), the arithmetic loops skip them.
+template <int QN, int P>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves(QN, P))))
+k_step(RlbmStepArgs a) {
   using S = typename Traits<P>::S;
   using A = typename Traits<P>::A;
-  const RlbmTable* __restrict__ tb = a.tab;
+  typedef const __attribute__((address_space(4))) int* OffPtr;
+  const TabPtr tb = as_tab(a.tab);
+  const RlbmLayout& L = a.L;
   const int Q = tb->c.Q;
   const int lb = xcd_remap(blockIdx.x, gridDim.x);
   const int y = lb / a.blocks_x;
-  const int x = (lb - y * a.blocks_x) * kBlock + threadIdx.x;
-  const bool active = x < a.nx;
-  const int xs = active ? x : a.nx - 1;
-  const S* __restrict__ src = (const S*)a.src;
+  const int x0 = (lb - y * a.blocks_x) * kBlock;
+  const int x = x0 + (int)threadIdx.x;
+  const bool active = x < L.nx;
+  const unsigned lo = (unsigned)((active ? x : L.nx - 1) - x0);   // lane offset from the block base
+  const long long base = (long long)(y + L.GY) * L.W + L.GX + x0;  // uniform
+  const S* __restrict__ src = (const S*)a.src + base;
   S* __restrict__ dst = (S*)a.dst;
 
-  A f[QCAP];
+  // source offsets of all classes, fetched together before any pull
+  const OffPtr offp = (OffPtr)a.offs;
+  int off[QN];
 #pragma unroll
-  for (int j = 0; j < QCAP; ++j) {
-    if (j < Q) {
-      int sx = xs, sy = y;
-      if (a.shift) {
-        sx = wrap_or_clamp(xs - tb->nx[j], a.nx, a.bc_x, a.x_small);
-        sy = wrap_or_clamp(y - tb->ny[j], a.ny, a.bc_y, a.y_small);
-      }
-      f[j] = to_arith<P>(src[(long long)j * a.plane + (long long)sy * a.nx + sx], tb, j);
-    } else {
-      f[j] = A(0);
-    }
+  for (int j = 0; j < QN; ++j) off[j] = offp[j];
+
+  // pull: f_j(x, t) = f*_j(x - n_j, t - 1) (exact streaming)
+  A f[QN];
+#pragma unroll
+  for (int j = 0; j < QN; ++j) {
+    const S v = (src + off[j])[lo];
+    if constexpr (P == RLBM_FP16_DEV) f[j] = (float)v * tb->rowf[j][RLBM_R_SCALE];
+    else f[j] = v;
   }
 
   // moments (eq. mj-discrete-second-moment); deviation modes add the exact
   // float64 moments of the reference state
   A m[9] = {A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0)};
+  // (the uniform guards of the arithmetic loops also keep the compiler from
+  // hoisting every class's table reads, which would spill registers)
 #pragma unroll
-  for (int j = 0; j < QCAP; ++j) {
+  for (int j = 0; j < QN; ++j) {
     if (j < Q) {
       A p0, px, py;
       if constexpr (P == RLBM_FP64) {
-        p0 = tb->p0[j]; px = tb->px[j]; py = tb->py[j];
+        p0 = tb->rowd[j][RLBM_R_P0]; px = tb->rowd[j][RLBM_R_PX]; py = tb->rowd[j][RLBM_R_PY];
       } else {
-        p0 = tb->fp0[j]; px = tb->fpx[j]; py = tb->fpy[j];
+        p0 = tb->rowf[j][RLBM_R_P0]; px = tb->rowf[j][RLBM_R_PX]; py = tb->rowf[j][RLBM_R_PY];
       }
       const A a0 = f[j] * p0, ax = f[j] * px, ay = f[j] * py;
       m[0] += a0; m[1] += ax; m[2] += ay;
@@ -158,11 +214,11 @@ __global__ void __launch_bounds__(kBlock) k_step(RlbmStepArgs a) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) md[k] = (P == RLBM_FP64) ? (double)m[k] : tb->c.ref_mom[k] + (double)m[k];
 
-  Macro mac = macroscopic(tb->c, md[0], md[1], md[2], md[3], md[4], md[5], md[6], md[7], md[8], a.landau_tol,
-                          a.landau_maxit);
+  Macro mac = macroscopic(tb, md[0], md[1], md[2], md[3], md[4], md[5], md[6], md[7], md[8], a.landau_tol,
+                          a.landau_maxit, a.landau_method);
   const double tau = a.tau_mode == RLBM_TAU_CONST ? a.tau : tau_eta_over_s(a.tk1, a.tk2, mac.n, mac.T);
   double b[RLBM_NB];
-  projections(tb->c, mac.T, mac.R, mac.gamma, mac.gamma * mac.ux, mac.gamma * mac.uy, b);
+  projections(tb, mac.T, mac.R, mac.gamma, mac.gamma * mac.ux, mac.gamma * mac.uy, b);
   // Anderson-Witting frequency p_i.U/(p_i^0 tau) = gamma (1 - v0 n_i.u)/tau (eq. discrete-relativistic-boltzmann)
   const double w0 = mac.gamma / tau;
   const double wx = -w0 * tb->c.v0 * mac.ux, wy = -w0 * tb->c.v0 * mac.uy;
@@ -171,26 +227,41 @@ __global__ void __launch_bounds__(kBlock) k_step(RlbmStepArgs a) {
   for (int k = 0; k < RLBM_NB; ++k) nb[k] = (A)(mac.n * b[k] - (P == RLBM_FP64 ? 0.0 : tb->c.nb_ref[k]));
   const A W0 = (A)w0, WX = (A)wx, WY = (A)wy;
 
-  const long long o = (long long)y * a.nx + xs;
+  // equilibrium (eq. mj-discrete-feq) and relaxation, stored at the own site
 #pragma unroll
-  for (int j = 0; j < QCAP; ++j) {
+  for (int j = 0; j < QN; ++j) {
     if (j < Q) {
       A feq, dx, dy;
       if constexpr (P == RLBM_FP64) {
-        feq = nb[0] * tb->M[0][j];
+        const auto* r = tb->rowd[j];
+        feq = nb[0] * r[0];
 #pragma unroll
-        for (int k = 1; k < RLBM_NB; ++k) feq = fma(nb[k], tb->M[k][j], feq);
-        dx = tb->dnx[j]; dy = tb->dny[j];
+        for (int k = 1; k < RLBM_NB; ++k) feq = fma(nb[k], r[k], feq);
+        dx = r[RLBM_R_NX]; dy = r[RLBM_R_NY];
       } else {
-        feq = nb[0] * tb->Mf[0][j];
+        const auto* r = tb->rowf[j];
+        feq = nb[0] * r[0];
 #pragma unroll
-        for (int k = 1; k < RLBM_NB; ++k) feq = fma(nb[k], tb->Mf[k][j], feq);
-        dx = tb->fnx[j]; dy = tb->fny[j];
+        for (int k = 1; k < RLBM_NB; ++k) feq = fma(nb[k], r[k], feq);
+        dx = r[RLBM_R_NX]; dy = r[RLBM_R_NY];
       }
       const A om = fma(WY, dy, fma(WX, dx, W0));
-      const A out = fma(-om, f[j] - feq, f[j]);
-      if (active) dst[(long long)j * a.plane + o] = to_store<P>(out, tb, j);
+      f[j] = fma(-om, f[j] - feq, f[j]);
+      S out;
+      if constexpr (P == RLBM_FP16_DEV) out = (_Float16)(f[j] * tb->rowf[j][RLBM_R_INVSCALE]);
+      else out = f[j];
+      if (active) (dst + ((long long)j * L.plane + base))[lo] = out;
     }
+  }
+
+  // ghost copies are needed only near the lattice edges (uniform test)
+  const unsigned ym = ghost_mask(y, L.ny, L.Sy, L.bc_y);
+  const bool xedge = x0 < L.Sx || x0 + kBlock > L.nx - L.Sx;
+  if ((xedge || ym != 0u) && active) {
+    const unsigned xm = xedge ? ghost_mask(x, L.nx, L.Sx, L.bc_x) : 0u;
+#pragma unroll
+    for (int j = 0; j < QN; ++j)
+      if (j < Q) store_ghosts(dst + (long long)j * L.plane, L, x, y, xm, ym, to_store<P>(f[j], tb, j));
   }
   block_stats(a.slots, lb, active ? mac.flags : 0u, active ? (unsigned)mac.iters : 0u);
 }
@@ -200,19 +271,17 @@ __global__ void __launch_bounds__(kBlock) k_step(RlbmStepArgs a) {
 template <int P>
 __global__ void __launch_bounds__(kBlock) k_moments(RlbmMomArgs a) {
   using S = typename Traits<P>::S;
-  const RlbmTable* __restrict__ tb = a.tab;
+  const TabPtr tb = as_tab(a.tab);
+  const RlbmLayout& L = a.L;
   const long long site = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (site >= (long long)a.nx * a.ny) return;
-  const int y = (int)(site / a.nx), x = (int)(site - (long long)y * a.nx);
+  if (site >= (long long)L.nx * L.ny) return;
+  const int y = (int)(site / L.nx), x = (int)(site - (long long)y * L.nx);
   const S* __restrict__ src = (const S*)a.src;
   double m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int j = 0; j < tb->c.Q; ++j) {
-    int sx = x, sy = y;
-    if (a.shift) {
-      sx = wrap_or_clamp(x - tb->nx[j], a.nx, a.bc_x, a.x_small);
-      sy = wrap_or_clamp(y - tb->ny[j], a.ny, a.bc_y, a.y_small);
-    }
-    const double f = (double)to_arith<P>(src[(long long)j * a.plane + (long long)sy * a.nx + sx], tb, j);
+    const int sx = a.shift ? x - tb->nx[j] : x, sy = a.shift ? y - tb->ny[j] : y;
+    const double f =
+        (double)to_arith<P>(src[(long long)j * L.plane + (long long)(sy + L.GY) * L.W + sx + L.GX], tb, j);
     const double p0 = tb->p0[j], px = tb->px[j], py = tb->py[j];
     m[0] += f * p0; m[1] += f * px; m[2] += f * py;
     m[3] += f * p0 * p0; m[4] += f * p0 * px; m[5] += f * p0 * py;
@@ -220,8 +289,8 @@ __global__ void __launch_bounds__(kBlock) k_moments(RlbmMomArgs a) {
   }
   if (P != RLBM_FP64)
     for (int k = 0; k < 9; ++k) m[k] += tb->c.ref_mom[k];
-  Macro mac = macroscopic(tb->c, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[8], a.landau_tol,
-                          a.landau_maxit);
+  Macro mac = macroscopic(tb, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[8], a.landau_tol,
+                          a.landau_maxit, a.landau_method);
   if (a.n) a.n[site] = mac.n;
   if (a.eps) a.eps[site] = mac.eps;
   if (a.T) a.T[site] = mac.T;
@@ -229,7 +298,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(RlbmMomArgs a) {
   if (a.ux) a.ux[site] = mac.ux;
   if (a.uy) a.uy[site] = mac.uy;
   if (a.raw9) {
-    const long long S2 = (long long)a.nx * a.ny;
+    const long long S2 = (long long)L.nx * L.ny;
     for (int k = 0; k < 9; ++k) a.raw9[k * S2 + site] = m[k];
   }
 }
@@ -239,32 +308,41 @@ __global__ void __launch_bounds__(kBlock) k_moments(RlbmMomArgs a) {
 template <int P>
 __global__ void __launch_bounds__(kBlock) k_init(RlbmInitArgs a) {
   using S = typename Traits<P>::S;
-  const RlbmTable* __restrict__ tb = a.tab;
+  const TabPtr tb = as_tab(a.tab);
+  const RlbmLayout& L = a.L;
   const long long site = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (site >= (long long)a.nx * a.ny) return;
+  if (site >= (long long)L.nx * L.ny) return;
+  const int y = (int)(site / L.nx), x = (int)(site - (long long)y * L.nx);
   const double n = a.n[site], T = a.T[site], ux = a.ux[site], uy = a.uy[site];
   const double g = 1.0 / sqrt(1.0 - ux * ux - uy * uy);
   double b[RLBM_NB];
-  projections(tb->c, T, k1k2_ratio(tb->c.zeta / T), g, g * ux, g * uy, b);
+  projections(tb, T, k1k2_ratio(tb->c.zeta / T), g, g * ux, g * uy, b);
   double nb[RLBM_NB];
   for (int k = 0; k < RLBM_NB; ++k) nb[k] = n * b[k] - (P == RLBM_FP64 ? 0.0 : tb->c.nb_ref[k]);
   S* __restrict__ dst = (S*)a.dst;
+  const long long o = (long long)(y + L.GY) * L.W + x + L.GX;
   for (int j = 0; j < tb->c.Q; ++j) {
     double fe = 0.0;
     for (int k = 0; k < RLBM_NB; ++k) fe = fma(nb[k], tb->M[k][j], fe);
-    dst[(long long)j * a.plane + site] = to_store<P>((typename Traits<P>::A)fe, tb, j);
+    dst[(long long)j * L.plane + o] = to_store<P>((typename Traits<P>::A)fe, tb, j);
   }
 }
 
 // ------------------------------------------------------------------ dispatch
 
 using StepFn = void (*)(RlbmStepArgs);
-constexpr int kQcaps[] = {24, 48, 80, 160};
 
+// Class-count buckets: exact fits for the configured stencils (19: zeta = 1
+// in 1D, 39: G1..G6 in 2D, 44: zeta = 1 in 2D, 73: the 133-population stencil
+// in 2D) and padded buckets for any other stencil.
 template <int P>
 StepFn step_kernel(int Q) {
+  if (Q <= 19) return k_step<19, P>;
   if (Q <= 24) return k_step<24, P>;
+  if (Q <= 39) return k_step<39, P>;
+  if (Q <= 44) return k_step<44, P>;
   if (Q <= 48) return k_step<48, P>;
+  if (Q <= 73) return k_step<73, P>;
   if (Q <= 80) return k_step<80, P>;
   return k_step<160, P>;
 }
@@ -292,11 +370,12 @@ struct rlbm_ctx {
   rlbm_lattice_desc lat;
   void* buf[2] = {nullptr, nullptr};
   size_t pop_bytes = 0;
-  long long plane = 0;
+  RlbmLayout L;
   int cur = 0;
   int shifted = 0;
   long long steps = 0;
   RlbmSlot* d_slots = nullptr;
+  int* d_offs = nullptr;  // [0, QMAX): local read offsets, [QMAX, 2 QMAX): pull offsets
   int nblocks = 0, blocks_x = 0;
   double tk1 = 0, tk2 = 0;
   char err[512] = {0};
@@ -329,6 +408,7 @@ extern "C" int rlbm_init_stencil(rlbm_ctx** out, const rlbm_stencil_desc* desc, 
     delete c;
     return rc;
   }
+  rlbm_build_eos_table(desc->zeta, c->h_tab->eos);
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->d_tab, sizeof(RlbmTable));
   if (e == hipSuccess) e = hipMemcpy(c->d_tab, c->h_tab, sizeof(RlbmTable), hipMemcpyHostToDevice);
@@ -349,19 +429,34 @@ extern "C" int rlbm_destroy(rlbm_ctx* c) {
   (void)hipDeviceSynchronize();
   if (c->d_tab) (void)hipFree(c->d_tab);
   if (c->d_slots) (void)hipFree(c->d_slots);
+  if (c->d_offs) (void)hipFree(c->d_offs);
   delete c->h_tab;
   delete c;
   return RLBM_OK;
 }
 
-static long long plane_elems(int nx, int ny) {
-  long long s = (long long)nx * ny;
-  return (s + kPlaneAlign - 1) / kPlaneAlign * kPlaneAlign;
+// Plane layout: ghost columns padded to 32 elements so every interior row
+// starts on a 32-element boundary; ghost rows of the max |n_y|.
+static RlbmLayout make_layout(const RlbmConsts& k, int nx, int ny, int bc_x, int bc_y) {
+  RlbmLayout L;
+  L.nx = nx;
+  L.ny = ny;
+  L.Sx = k.sx_max;
+  L.Sy = k.sy_max;
+  L.GX = (L.Sx + 31) / 32 * 32;
+  L.GY = L.Sy;
+  L.W = (L.GX + nx + L.Sx + 31) / 32 * 32;
+  long long s = (long long)(ny + 2 * L.GY) * L.W;
+  L.plane = (s + kPlaneAlign - 1) / kPlaneAlign * kPlaneAlign;
+  L.bc_x = bc_x;
+  L.bc_y = bc_y;
+  return L;
 }
 
 extern "C" size_t rlbm_population_bytes(const rlbm_ctx* c, int nx, int ny) {
   if (!c || nx <= 0 || ny <= 0) return 0;
-  return (size_t)c->h_tab->c.Q * (size_t)plane_elems(nx, ny) * elem_size(c->h_tab->c.precision);
+  RlbmLayout L = make_layout(c->h_tab->c, nx, ny, 0, 0);
+  return (size_t)c->h_tab->c.Q * (size_t)L.plane * elem_size(c->h_tab->c.precision);
 }
 
 extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n, const double* T,
@@ -390,10 +485,26 @@ extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const
   c->lat = *lat;
   if (!(c->lat.landau_tol > 0)) c->lat.landau_tol = k.precision == RLBM_FP64 ? 1e-14 : 1e-10;
   if (c->lat.landau_maxit <= 0) c->lat.landau_maxit = 200;
+  if (c->lat.landau_method != RLBM_LANDAU_NEWTON && c->lat.landau_method != RLBM_LANDAU_FIXED_POINT)
+    return fail(c, RLBM_EINVAL, "invalid Landau method");
   c->buf[0] = popA;
   c->buf[1] = popB;
   c->pop_bytes = pop_bytes;
-  c->plane = plane_elems(lat->nx, lat->ny);
+  c->L = make_layout(k, lat->nx, lat->ny, lat->bc_x, lat->bc_y);
+  if ((long long)k.Q * c->L.plane >= (1LL << 31)) return fail(c, RLBM_EINVAL, "lattice too large for 32-bit offsets");
+  {
+    std::vector<int> offs(2 * RLBM_QMAX, 0);
+    for (int j = 0; j < k.Q; ++j) {
+      offs[j] = (int)(j * c->L.plane);
+      offs[RLBM_QMAX + j] = (int)(j * c->L.plane - (long long)c->h_tab->ny[j] * c->L.W - c->h_tab->nx[j]);
+    }
+    for (int j = k.Q; j < RLBM_QMAX; ++j) {  // padding classes read class 0's source
+      offs[j] = offs[0];
+      offs[RLBM_QMAX + j] = offs[RLBM_QMAX];
+    }
+    if (!c->d_offs) HIPCHECK(c, hipMalloc((void**)&c->d_offs, sizeof(int) * 2 * RLBM_QMAX));
+    HIPCHECK(c, hipMemcpy(c->d_offs, offs.data(), sizeof(int) * 2 * RLBM_QMAX, hipMemcpyHostToDevice));
+  }
   c->cur = 0;
   c->shifted = 0;
   c->steps = 0;
@@ -413,9 +524,7 @@ extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const
   }
   RlbmInitArgs ia;
   ia.dst = popA;
-  ia.plane = c->plane;
-  ia.nx = lat->nx;
-  ia.ny = lat->ny;
+  ia.L = c->L;
   ia.n = n; ia.T = T; ia.ux = ux; ia.uy = uy;
   ia.tab = c->d_tab;
   long long sites = (long long)lat->nx * lat->ny;
@@ -430,23 +539,13 @@ extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const
   return RLBM_OK;
 }
 
-static void fill_geometry(const rlbm_ctx* c, int& x_small, int& y_small) {
-  x_small = c->lat.nx <= c->h_tab->c.max_shift ? 1 : 0;
-  y_small = c->lat.ny <= c->h_tab->c.max_shift ? 1 : 0;
-}
-
 extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
   if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_step before rlbm_init_fields");
   if (nsteps < 0) return fail(c, RLBM_EINVAL, "negative step count");
   hipStream_t s = (hipStream_t)stream;
   RlbmStepArgs a;
-  a.plane = c->plane;
-  a.nx = c->lat.nx;
-  a.ny = c->lat.ny;
-  a.bc_x = c->lat.bc_x;
-  a.bc_y = c->lat.bc_y;
-  fill_geometry(c, a.x_small, a.y_small);
+  a.L = c->L;
   a.blocks_x = c->blocks_x;
   a.tau_mode = c->lat.tau_mode;
   a.tau = c->lat.tau;
@@ -454,6 +553,7 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   a.tk2 = c->tk2;
   a.landau_tol = c->lat.landau_tol;
   a.landau_maxit = c->lat.landau_maxit;
+  a.landau_method = c->lat.landau_method;
   a.tab = c->d_tab;
   a.slots = c->d_slots;
   StepFn fn = select_step(c->h_tab->c.precision, c->h_tab->c.Q);
@@ -461,6 +561,7 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
     a.src = c->buf[c->cur];
     a.dst = c->buf[1 - c->cur];
     a.shift = c->shifted;
+    a.offs = c->d_offs + (c->shifted ? RLBM_QMAX : 0);
     hipLaunchKernelGGL(fn, dim3(c->nblocks), dim3(kBlock), 0, s, a);
     HIPCHECK(c, hipGetLastError());
     c->cur ^= 1;
@@ -476,18 +577,14 @@ extern "C" int rlbm_moments(rlbm_ctx* c, double* n, double* eps, double* T, doub
   if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_moments before rlbm_init_fields");
   RlbmMomArgs a;
   a.src = c->buf[c->cur];
-  a.plane = c->plane;
-  a.nx = c->lat.nx;
-  a.ny = c->lat.ny;
-  a.bc_x = c->lat.bc_x;
-  a.bc_y = c->lat.bc_y;
+  a.L = c->L;
   a.shift = c->shifted;
-  fill_geometry(c, a.x_small, a.y_small);
   a.landau_tol = c->lat.landau_tol;
   a.landau_maxit = c->lat.landau_maxit;
+  a.landau_method = c->lat.landau_method;
   a.tab = c->d_tab;
   a.n = n; a.eps = eps; a.T = T; a.P = P; a.ux = ux; a.uy = uy; a.raw9 = raw9;
-  long long sites = (long long)a.nx * a.ny;
+  long long sites = (long long)a.L.nx * a.L.ny;
   dim3 grid((unsigned)((sites + kBlock - 1) / kBlock));
   hipStream_t s = (hipStream_t)stream;
   switch (c->h_tab->c.precision) {

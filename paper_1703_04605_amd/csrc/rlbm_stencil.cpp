@@ -35,21 +35,27 @@ typedef long double ld;
 
 namespace {
 
-ld besselk_ld(int nu, ld x) {
-  const ld h = 1.0L / 32.0L;
-  ld s = 0.5L * expl(-x);
+// exp(x) K_nu(x) = int_0^inf exp(-x (cosh t - 1)) cosh(nu t) dt.  Only ratios
+// of K's at one argument are ever used, so the scaled form avoids underflow.
+ld besselk_scaled_ld(int nu, ld x) {
+  // Trapezoid rule: for this entire integrand the error decays like
+  // exp(-pi^2/h), and near t = 0 it is a Gaussian of width 1/sqrt(x), so h is
+  // also kept below half that width.
+  const ld h = std::min(1.0L / 8.0L, 0.5L / sqrtl(x));
+  ld s = 0.5L;
   for (int k = 1; k < 100000; ++k) {
     ld t = k * h;
-    ld v = expl(-x * coshl(t)) * coshl(nu * t);
+    ld ch = coshl(t);
+    ld v = expl(-x * (ch - 1.0L)) * coshl(nu * t);
     s += v;
-    if (v < 1e-24L * s && x * (coshl(t) - 1.0L) > 40.0L) break;
+    if (x * (ch - 1.0L) > 60.0L + nu * t && v < 1e-22L * s) break;
   }
   return s * h;
 }
 
 // S_a = int_0^inf exp(-m (cosh t - 1)) cosh^a t sinh^2 t dt, a = 0..4
 void energy_integrals(ld m, ld S[5]) {
-  const ld h = 1.0L / 64.0L;
+  const ld h = std::min(1.0L / 8.0L, 0.5L / sqrtl(m));
   for (int a = 0; a < 5; ++a) S[a] = 0.0L;
   for (int k = 1; k < 200000; ++k) {
     ld t = k * h;
@@ -85,9 +91,9 @@ struct Basis {
   ld m, k1, k2, k3;
   ld A, B, C, D, E, a1, c1, c0, d0;
   explicit Basis(ld mbar) : m(mbar) {
-    k1 = besselk_ld(1, m);
-    k2 = besselk_ld(2, m);
-    k3 = besselk_ld(3, m);
+    k1 = besselk_scaled_ld(1, m);   // common factor exp(-m) cancels in every ratio below
+    k2 = besselk_scaled_ld(2, m);
+    k3 = besselk_scaled_ld(3, m);
     ld den = m * k1 * k1 + 3 * k2 * k1 - m * k2 * k2;
     A = sqrtl(m * (m + k2 * (3 * k1 - m * k2) / (k1 * k1)));
     B = sqrtl(m * k2 / k1);
@@ -228,7 +234,7 @@ void set_err(char* err, size_t len, const char* msg) {
 }  // namespace
 
 // Bessel ratio K1/K2 in long double (host reference state only)
-static ld k1k2_ld(ld z) { return besselk_ld(1, z) / besselk_ld(2, z); }
+static ld k1k2_ld(ld z) { return besselk_scaled_ld(1, z) / besselk_scaled_ld(2, z); }
 
 int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTable* tab, char* err,
                      size_t errlen) {
@@ -348,8 +354,16 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
     set_err(err, errlen, "stencil has more population classes than the library supports");
     return RLBM_EINVAL;
   }
-  int max_shift = 0;
-  for (auto& p : pops) max_shift = std::max(max_shift, std::max(abs(p.n[0]), d->dim == 2 ? abs(p.n[1]) : 0));
+  int max_shift = 0, sx_max = 0, sy_max = 0;
+  for (auto& p : pops) {
+    sx_max = std::max(sx_max, abs(p.n[0]));
+    if (d->dim == 2) sy_max = std::max(sy_max, abs(p.n[1]));
+  }
+  max_shift = std::max(sx_max, sy_max);
+  if (max_shift > 16) {
+    set_err(err, errlen, "displacements above 16 lattice sites are not supported");
+    return RLBM_EINVAL;
+  }
 
   if (info) {
     memset(info, 0, sizeof(*info));
@@ -370,6 +384,8 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
   c.dim = d->dim;
   c.precision = d->precision;
   c.max_shift = max_shift;
+  c.sx_max = sx_max;
+  c.sy_max = sy_max;
   c.zeta = d->zeta;
   c.v0 = (double)v0;
   c.a1 = (double)B.a1;
@@ -435,7 +451,21 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
     for (int k = 0; k < RLBM_NB; ++k) {
       tab->M[k][j] = (double)Mld[j][k];
       tab->Mf[k][j] = (float)Mld[j][k];
+      tab->rowf[j][k] = (float)Mld[j][k];
+      tab->rowd[j][k] = (double)Mld[j][k];
     }
+    tab->rowf[j][RLBM_R_NX] = tab->fnx[j];
+    tab->rowf[j][RLBM_R_NY] = tab->fny[j];
+    tab->rowf[j][RLBM_R_P0] = tab->fp0[j];
+    tab->rowf[j][RLBM_R_PX] = tab->fpx[j];
+    tab->rowf[j][RLBM_R_PY] = tab->fpy[j];
+    tab->rowf[j][RLBM_R_SCALE] = tab->scale[j];
+    tab->rowf[j][RLBM_R_INVSCALE] = tab->inv_scale[j];
+    tab->rowd[j][RLBM_R_NX] = tab->dnx[j];
+    tab->rowd[j][RLBM_R_NY] = tab->dny[j];
+    tab->rowd[j][RLBM_R_P0] = tab->p0[j];
+    tab->rowd[j][RLBM_R_PX] = tab->px[j];
+    tab->rowd[j][RLBM_R_PY] = tab->py[j];
   }
   return RLBM_OK;
 }
@@ -463,6 +493,78 @@ extern "C" int rlbm_class_table(const rlbm_stencil_desc* desc, int cap, int* dis
     mom[3 * j + 1] = tab.px[j];
     mom[3 * j + 2] = tab.py[j];
     for (int k = 0; k < RLBM_NB; ++k) M[RLBM_NB * j + k] = tab.M[k][j];
+  }
+  return RLBM_OK;
+}
+
+// Temperature T(u) solving u + zeta = 3T + zeta K1(zeta/T)/K2(zeta/T)
+// (eq. relativistic-eos, T_R = 1) by Newton's method from above (the function
+// is convex in T); long double.
+static ld eos_temperature_ld(ld u, ld zeta) {
+  ld e = u + zeta;
+  ld t = std::min(u / 1.5L, e / 3.0L);
+  bool done = false;
+  for (int it = 0; it < 40; ++it) {
+    ld z = zeta / t;
+    ld r = k1k2_ld(z);
+    ld F = 3 * t + zeta * r - e;
+    ld dF = 3 - z * z * r * r - 3 * z * r + z * z;
+    ld d = F / dF;
+    t -= d;
+    if (done) break;
+    if (fabsl(d) <= 1e-12L * t) done = true;  // quadratic convergence: one more step
+  }
+  return t;
+}
+
+void rlbm_build_eos_table(double zeta, double (*out)[RLBM_EOS_DEG]) {
+  const int D = RLBM_EOS_DEG;
+  const ld pi = 3.141592653589793238462643383279502884L;
+  for (int o = 0; o < RLBM_EOS_NOCT; ++o) {
+    ld base = ldexpl(1.0L, RLBM_EOS_KMIN + o);
+    for (int piece = 0; piece < 4; ++piece) {
+      ld a = base * (1.0L + 0.25L * piece), b = base * (1.0L + 0.25L * (piece + 1));
+      ld g[RLBM_EOS_DEG];
+      for (int i = 0; i < D; ++i) {
+        ld t = cosl(pi * (i + 0.5L) / D);
+        ld u = a + (b - a) * (t + 1.0L) * 0.5L;
+        g[i] = eos_temperature_ld(u, (ld)zeta) / u;
+      }
+      for (int j = 0; j < D; ++j) {
+        ld s = 0;
+        for (int i = 0; i < D; ++i) s += g[i] * cosl(pi * j * (i + 0.5L) / D);
+        s *= 2.0L / D;
+        if (j == 0) s *= 0.5L;
+        out[o * 4 + piece][j] = (double)s;
+      }
+    }
+  }
+}
+
+extern "C" int rlbm_eos_temperature_host(double zeta, const double* e, int n, double* T) {
+  if (!(zeta > 0) || !e || !T || n < 0) return RLBM_EINVAL;
+  std::unique_ptr<double[][RLBM_EOS_DEG]> tab(new double[RLBM_EOS_NOCT * 4][RLBM_EOS_DEG]);
+  rlbm_build_eos_table(zeta, tab.get());
+  for (int i = 0; i < n; ++i) {
+    double u = e[i] - zeta;
+    int ex;
+    double m = frexp(u, &ex);
+    int o = ex - 1 - RLBM_EOS_KMIN;
+    if (!(u > 0) || o < 0 || o >= RLBM_EOS_NOCT) {
+      T[i] = (double)eos_temperature_ld((ld)u, (ld)zeta);
+      continue;
+    }
+    double m2 = 2.0 * m;
+    int piece = std::min((int)((m2 - 1.0) * 4.0), 3);
+    double t = (m2 - 1.0 - 0.25 * piece) * 8.0 - 1.0;
+    const double* c = tab[o * 4 + piece];
+    double b1 = 0, b2 = 0;
+    for (int j = RLBM_EOS_DEG - 1; j >= 1; --j) {
+      double b0 = fma(2.0 * t, b1, c[j] - b2);
+      b2 = b1;
+      b1 = b0;
+    }
+    T[i] = u * fma(t, b1, c[0] - b2);
   }
   return RLBM_OK;
 }

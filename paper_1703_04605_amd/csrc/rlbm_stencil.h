@@ -11,3 +11,7 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
                      size_t errlen);
 const char* rlbm_global_error();
 void rlbm_set_global_error(const char* msg);
+
+// Chebyshev pieces of the inverse equation of state T(u)/u for mbar = zeta
+// (layout of RlbmTable::eos).
+void rlbm_build_eos_table(double zeta, double (*out)[RLBM_EOS_DEG]);

@@ -6,6 +6,20 @@
 #define RLBM_QMAX 160   // population classes per stencil (6 groups: <= 150)
 #define RLBM_NB 10      // second-order polynomials that survive U_z = 0
 
+// Inverse equation of state T(u), u = eps/n - mbar (kinetic energy per
+// particle): T/u as a Chebyshev series on each quarter of each octave
+// 2^k <= u < 2^(k+1), k = RLBM_EOS_KMIN .. RLBM_EOS_KMIN + RLBM_EOS_NOCT - 1.
+#define RLBM_EOS_KMIN (-14)
+#define RLBM_EOS_NOCT 28
+#define RLBM_EOS_DEG 14
+
+#define RLBM_ROWF 18
+#define RLBM_ROWD 16
+enum { RLBM_R_NX = 10, RLBM_R_NY, RLBM_R_P0, RLBM_R_PX, RLBM_R_PY, RLBM_R_SCALE, RLBM_R_INVSCALE };
+
+#define RLBM_LANDAU_NEWTON 0      // Newton on det(lambda I - T eta) from lambda = T^00
+#define RLBM_LANDAU_FIXED_POINT 1 // eps = T^00 - T^0i u_i, u_i = (T^0i - T^ij u_j)/eps
+
 // Polynomial order of the 10 in-plane coefficients (Appendix A labels):
 //   0: J^(0)     1: J^(1)_0   2: J^(1)_x   3: J^(1)_y   4: J^(2)_00
 //   5: J^(2)_0x  6: J^(2)_0y  7: J^(2)_xx  8: J^(2)_yy  9: J^(2)_xy
@@ -17,6 +31,7 @@ struct RlbmConsts {
   int dim;        // 1 or 2
   int precision;  // RLBM_FP64 / RLBM_FP32_DEV / RLBM_FP16_DEV
   int max_shift;
+  int sx_max, sy_max;  // max |n_x|, max |n_y| over the classes
   double zeta;    // mbar = m / T_R
   double v0;
   // Appendix A constants at mbar (T_R = 1):
@@ -42,6 +57,12 @@ struct RlbmTable {
   float fp0[RLBM_QMAX], fpx[RLBM_QMAX], fpy[RLBM_QMAX];
   float Mf[RLBM_NB][RLBM_QMAX];
   float scale[RLBM_QMAX], inv_scale[RLBM_QMAX];  // FP16: d_j = scale_j * h_j
+  double eos[RLBM_EOS_NOCT * 4][RLBM_EOS_DEG];     // inverse EOS pieces
+  // Per-class rows read by the step kernel with one wide scalar load each:
+  // [M_j0 .. M_j9, n_x, n_y, p^0, p^x, p^y, scale, 1/scale, 0] (float) and
+  // [M_j0 .. M_j9, n_x, n_y, p^0, p^x, p^y, 0] (double).
+  float rowf[RLBM_QMAX][RLBM_ROWF];
+  double rowd[RLBM_QMAX][RLBM_ROWD];
 };
 
 // Per-block health / statistics slot, accumulated by the step kernel.
@@ -51,38 +72,51 @@ struct RlbmSlot {
   uint64_t iter_sum;
 };
 
+// Storage of one population plane: (ny + 2 GY) rows of W elements; site
+// (x, y) lives at (y + GY) W + x + GX.  The ghost columns [-Sx, 0), [nx, nx+Sx)
+// and rows [-Sy, 0), [ny, ny+Sy) hold copies written by the owner sites under
+// the boundary rule, so pulls f_j(x - n_j) need no wrap or clamp.
+struct RlbmLayout {
+  long long plane;  // elements per plane (padded)
+  int W, GX, GY;
+  int nx, ny;
+  int Sx, Sy;       // ghost widths actually used (max shifts)
+  int bc_x, bc_y;
+};
+
 struct RlbmStepArgs {
   const void* src;
   void* dst;
-  long long plane;     // elements per population plane
-  int nx, ny;
-  int bc_x, bc_y;      // RLBM_BC_*
+  RlbmLayout L;
+  const int* offs;     // per class: element offset of the source of f_j relative to
+                       // the site's own storage index in plane 0 (j*plane, minus
+                       // n_y W + n_x when pulling); QMAX entries
   int shift;           // 1: pull f_j(x - n_j) (post-collision state), 0: read f_j(x)
-  int x_small, y_small;  // lattice side <= max shift: use modular wrap
   int blocks_x;        // blocks per row
   int tau_mode;
   double tau;          // constant tau
   double tk1, tk2;     // eta/s: tau = 1/2 + tk1 (4 - ln(tk2 n / T^3)) / T
   double landau_tol;
   int landau_maxit;
+  int landau_method;   // RLBM_LANDAU_*
   const RlbmTable* tab;
   RlbmSlot* slots;     // one per block (logical index)
 };
 
 struct RlbmMomArgs {
   const void* src;
-  long long plane;
-  int nx, ny, bc_x, bc_y, shift, x_small, y_small;
+  RlbmLayout L;
+  int shift;
   double landau_tol;
   int landau_maxit;
+  int landau_method;
   const RlbmTable* tab;
   double *n, *eps, *T, *P, *ux, *uy, *raw9;
 };
 
 struct RlbmInitArgs {
   void* dst;
-  long long plane;
-  int nx, ny;
+  RlbmLayout L;
   const double *n, *T, *ux, *uy;
   const RlbmTable* tab;
 };

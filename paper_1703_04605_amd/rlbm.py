@@ -19,6 +19,7 @@ RLBM_ENUMERIC = -4
 RLBM_ESTATE = -5
 
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2}
+LANDAU = {"newton": 0, "fixed_point": 1}
 BC = {"periodic": 0, "outflow": 1}
 TAU_CONST, TAU_ETA_OVER_S = 0, 1
 ELEM_DTYPE = {"fp64": "float64", "fp32": "float32", "fp16": "float16"}
@@ -28,7 +29,7 @@ H_NAN, H_LANDAU, H_SUPERLUMINAL, H_RANGE, H_EOS = 1, 2, 4, 8, 16
 EXPORTS = ["rlbm_init_stencil", "rlbm_solve_stencil", "rlbm_class_table", "rlbm_destroy",
            "rlbm_population_bytes", "rlbm_init_fields", "rlbm_step", "rlbm_moments",
            "rlbm_get_health", "rlbm_step_count", "rlbm_save_state", "rlbm_load_state",
-           "rlbm_last_error"]
+           "rlbm_last_error", "rlbm_eos_temperature_host"]
 
 
 class RlbmError(RuntimeError):
@@ -55,7 +56,7 @@ class LatticeDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
                 ("tau_mode", ctypes.c_int), ("tau", ctypes.c_double), ("eta_over_s", ctypes.c_double),
                 ("T_R_GeV", ctypes.c_double), ("n_unit_fm3", ctypes.c_double), ("dx_fm", ctypes.c_double),
-                ("landau_tol", ctypes.c_double), ("landau_maxit", ctypes.c_int)]
+                ("landau_tol", ctypes.c_double), ("landau_maxit", ctypes.c_int), ("landau_method", ctypes.c_int)]
 
 
 _lib = None
@@ -87,6 +88,7 @@ def lib():
     L.rlbm_save_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(ctypes.c_int), vp]
     L.rlbm_load_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_longlong, ci, vp]
+    L.rlbm_eos_temperature_host.argtypes = [cd, dp, ci, dp]
     L.rlbm_last_error.argtypes = [vp]
     L.rlbm_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -136,6 +138,16 @@ def class_table(bases, zeta, v0, dim=2):
             np.array(M[:10 * q]).reshape(q, 10))
 
 
+def eos_temperature_host(zeta, e):
+    """Host evaluation of the library's inverse-EOS table (no GPU)."""
+    import numpy as np
+    e = np.ascontiguousarray(e, dtype=np.float64)
+    T = np.empty_like(e)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().rlbm_eos_temperature_host(float(zeta), e.ctypes.data_as(dp), e.size, T.ctypes.data_as(dp)))
+    return T
+
+
 class Solver:
     """One lattice on the current CUDA (HIP) device.
 
@@ -170,7 +182,8 @@ class Solver:
     def population_bytes(self, nx, ny):
         return lib().rlbm_population_bytes(self.ctx, nx, ny)
 
-    def init_fields(self, n, T, ux, uy, bc=("periodic", "periodic"), tau=1.0, landau_tol=0.0, landau_maxit=0):
+    def init_fields(self, n, T, ux, uy, bc=("periodic", "periodic"), tau=1.0, landau_tol=0.0, landau_maxit=0,
+                    landau="newton"):
         """n, T, ux, uy: CUDA float64 tensors [ny, nx].  tau: float, or dict with
         eta_over_s, T_R_GeV, n_unit_fm3, dx_fm for the eta/s rule."""
         torch = self.torch
@@ -179,10 +192,11 @@ class Solver:
             assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous() and tuple(a.shape) == (ny, nx)
         if isinstance(tau, dict):
             lat = LatticeDesc(nx, ny, BC[bc[0]], BC[bc[1]], TAU_ETA_OVER_S, 0.0, tau["eta_over_s"],
-                              tau["T_R_GeV"], tau["n_unit_fm3"], tau["dx_fm"], landau_tol, landau_maxit)
+                              tau["T_R_GeV"], tau["n_unit_fm3"], tau["dx_fm"], landau_tol, landau_maxit,
+                              LANDAU[landau])
         else:
             lat = LatticeDesc(nx, ny, BC[bc[0]], BC[bc[1]], TAU_CONST, float(tau), 0, 0, 0, 0,
-                              landau_tol, landau_maxit)
+                              landau_tol, landau_maxit, LANDAU[landau])
         nbytes = self.population_bytes(nx, ny)
         self.pop = [torch.empty(nbytes, dtype=torch.uint8, device=n.device) for _ in range(2)]
         self._fields = (n, T, ux, uy)

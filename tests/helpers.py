@@ -11,11 +11,11 @@ def to_dev(arrs):
 
 
 def gpu_run(st, fields, steps, precision="fp64", dim=2, bc=("periodic", "periodic"), tau=1.0, checkpoints=None,
-            landau_tol=0.0, landau_maxit=0):
+            landau_tol=0.0, landau_maxit=0, landau="newton"):
     """Runs the library; returns {step: fields(numpy)} at the checkpoints."""
     from paper_1703_04605_amd import rlbm
     s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=dim, precision=precision)
-    s.init_fields(*to_dev(fields), bc=bc, tau=tau, landau_tol=landau_tol, landau_maxit=landau_maxit)
+    s.init_fields(*to_dev(fields), bc=bc, tau=tau, landau_tol=landau_tol, landau_maxit=landau_maxit, landau=landau)
     cps = sorted(set(checkpoints or [steps]))
     out, done = {}, 0
     for c in cps:

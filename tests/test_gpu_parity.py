@@ -46,6 +46,17 @@ def test_fp64_periodic_vs_full_stencil(name):
     assert max(errs.values()) < FP64_TOL, errs
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32", FP32_TOL)])
+def test_fixed_point_landau_vs_oracle(precision, tol):
+    """The plain fixed-point Landau iteration gives the same fields."""
+    st = workloads.STENCILS["zeta1"]
+    fields = workloads.random_smooth(300, 6, seed=12)
+    g, _ = gpu_run(st, fields, 5, precision=precision, tau=0.95, landau="fixed_point")
+    r = oracle_run(st, fields, 5, tau=0.95)
+    errs = field_errors(g[5], r[5])
+    assert max(errs.values()) < tol, errs
+
+
 def test_fp64_outflow_2d():
     st = workloads.STENCILS["zeta1"]
     fields = workloads.random_smooth(40, 30, seed=4)

@@ -91,3 +91,19 @@ def test_error_codes():
     with pytest.raises(rlbm.RlbmError) as e:           # mbar = 0.1: no positive window for this set
         rlbm.solve_stencil(workloads.STENCILS["zeta036"]["bases"], 0.1, 0.0)
     assert e.value.code == rlbm.RLBM_ENOSTENCIL
+
+
+@pytest.mark.parametrize("zeta", [0.36, 1.0, 5.0, 10.0])
+def test_inverse_eos_table_against_oracle(zeta):
+    """The GPU's inverse-EOS table (evaluated on the host) against the oracle's
+    bisection, over T in [1e-3, 1e3]; and it builds in well under a second."""
+    import time
+    from oracle import eos
+    T = np.geomspace(1e-3, 1e3, 2001)
+    e = eos.energy_per_particle(T, zeta)
+    t0 = time.perf_counter()
+    Tl = rlbm.eos_temperature_host(zeta, e)
+    assert time.perf_counter() - t0 < 2.0
+    # bounded by the conditioning of the inversion: ulp(e)/c_v with c_v >= 3/2
+    err = np.abs(Tl - T) / (np.finfo(float).eps * (e / 1.5 + T))
+    assert err.max() < 8.0, err.max()

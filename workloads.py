@@ -36,13 +36,16 @@ RIEMANN = {"P_left": 5.43, "T_left_GeV": 0.35, "P_right": 0.339, "T_right_GeV": 
 
 def riemann_1d(nx=800):
     """Quasi-1D shock tube: left/right constant states, u = 0, interface
-    between cells nx/2 - 1 and nx/2.  T_R = the left (hottest) temperature."""
-    TR = RIEMANN["T_left_GeV"]
+    between cells nx/2 - 1 and nx/2.  The temperature unit T_R is the geometric
+    mean of the two temperatures, so that the lattice temperatures (1.32 and
+    0.76) straddle T_R, around which the polynomial expansion is built; n is in
+    units of the left density."""
+    TR = (RIEMANN["T_left_GeV"] * RIEMANN["T_right_GeV"]) ** 0.5
     nL = RIEMANN["P_left"] / RIEMANN["T_left_GeV"]           # fm^-3
     nR = RIEMANN["P_right"] / RIEMANN["T_right_GeV"]
     left = np.arange(nx) < nx // 2
     n = np.where(left, 1.0, nR / nL)[None, :]
-    T = np.where(left, 1.0, RIEMANN["T_right_GeV"] / TR)[None, :]
+    T = np.where(left, RIEMANN["T_left_GeV"] / TR, RIEMANN["T_right_GeV"] / TR)[None, :]
     z = np.zeros((1, nx))
     tau = {"eta_over_s": RIEMANN["eta_over_s"], "T_R_GeV": TR, "n_unit_fm3": nL,
            "dx_fm": RIEMANN["domain_fm"] / nx}
