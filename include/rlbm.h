@@ -216,6 +216,46 @@ long long rlbm_step_count(const rlbm_ctx* ctx);
 int rlbm_save_state(rlbm_ctx* ctx, void* dst, size_t bytes, long long* step, int* layout_flag, void* stream);
 int rlbm_load_state(rlbm_ctx* ctx, const void* src, size_t bytes, long long step, int layout_flag, void* stream);
 
+/*
+ * Learned initial guess of the Landau-frame solve (an addition to the paper's
+ * method).  A 9 -> 64 -> 64 -> 64 -> 3 perceptron with SiLU activations maps
+ * the nine moments of a site divided by N^0 to (eps/N^0, u_x, u_y); inputs
+ * and outputs are standardised with norm = mx[9], sx[9], my[3], sy[3].
+ * params (9155 floats): W1 [64x9], b1[64], W2 [64x64], b2[64], W3 [64x64],
+ * b3[64], W4 [3x64], b4[3], row-major, z = W a + b.  The library keeps float32
+ * master weights and uses their bfloat16 roundings in every product with
+ * float32 accumulation.  rlbm_mlp_create copies params and norm (host) and
+ * allocates the training buffers for batches up to max_batch.
+ */
+typedef struct rlbm_mlp rlbm_mlp;
+int rlbm_mlp_create(rlbm_mlp** out, const float* params, const float* norm, int max_batch);
+int rlbm_mlp_destroy(rlbm_mlp* m);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the mean squared error
+ * of the standardised outputs.  raw9: device [B][9] moments (N^0, N^x, N^y,
+ * T^00, T^0x, T^0y, T^xx, T^xy, T^yy); target: device [B][3] (eps, u_x, u_y)
+ * of the converged Landau frame.  loss (host, nullable) receives the loss
+ * before the step (synchronises stream). */
+int rlbm_mlp_train_step(rlbm_mlp* m, const float* raw9, const float* target, int B, float lr, float* loss,
+                        void* stream);
+
+/* pred: device [B][3] = (eps, u_x, u_y) predicted from raw9 (device [B][9]). */
+int rlbm_mlp_predict(rlbm_mlp* m, const float* raw9, int B, float* pred, void* stream);
+
+/* Copies the float32 master weights and the last gradients (host, nullable). */
+int rlbm_mlp_get_params(rlbm_mlp* m, float* params, float* grads);
+
+/* Makes every later rlbm_step of ctx start its Landau solve from the network's
+ * guess (NULL: from T^00, or from u = 0 for the fixed point).  The network
+ * must outlive its use by ctx.  The solve that follows is unchanged, so the
+ * fields agree with the unguided path to the Landau tolerance. */
+int rlbm_set_landau_guess(rlbm_ctx* ctx, const rlbm_mlp* m);
+
+/* Diagnostic: the network's guess for the current state, evaluated by the
+ * same in-kernel inference as rlbm_step: out (device float32 [3][ny][nx]) =
+ * eps, u_x, u_y.  RLBM_ESTATE without fields or network. */
+int rlbm_landau_guess_fields(rlbm_ctx* ctx, float* out, void* stream);
+
 /* Last error message of ctx (or of the last failed context-less call when
  * ctx is NULL).  The string is owned by the library. */
 const char* rlbm_last_error(const rlbm_ctx* ctx);

@@ -19,10 +19,12 @@ def build(verbose=False):
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
     host_obj = os.path.join(HERE, "_build", "rlbm_stencil.o")
     dev_obj = os.path.join(HERE, "_build", "rlbm_lib.o")
+    mlp_obj = os.path.join(HERE, "_build", "rlbm_mlp.o")
     cmds = [
         ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, "rlbm_stencil.cpp"), "-o", host_obj],
+        [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "rlbm_mlp.hip"), "-o", mlp_obj],
         [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "rlbm_lib.hip"), "-o", dev_obj],
-        [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", dev_obj, host_obj, "-o", LIB + ".tmp"],
+        [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", dev_obj, mlp_obj, host_obj, "-o", LIB + ".tmp"],
     ]
     for cmd in cmds:
         if verbose:

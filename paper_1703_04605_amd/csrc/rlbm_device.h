@@ -123,17 +123,23 @@ __device__ __forceinline__ double eos_temperature_tab(TabPtr tb, double e, doubl
 //   p(l) = (l - T00)[(l + Txx)(l + Tyy) - Txy^2] + T0x^2 (l + Tyy)
 //          - 2 T0x T0y Txy + T0y^2 (l + Txx).
 // T^00 bounds eps from above and p is increasing and convex to the right of
-// its largest root, so the iterates decrease monotonically.  The velocity then
+// its largest root, so iterates started at T^00 decrease monotonically (a
+// start l0 below the root but above the inflection point of p jumps to the
+// right of the root first).  The velocity then
 // solves (eps delta_ij + T^ij) u_j = T^0i, the spatial rows of the eigenproblem.
 // Stops one iteration after the step falls below `thresh` (quadratic
 // convergence).  Returns the iteration count (maxit + 1 if the cap was hit).
 __device__ __forceinline__ int landau_newton(double T00, double T0x, double T0y, double Txx, double Txy,
                                              double Tyy, double thresh, int maxit, double& eps, double& ux,
-                                             double& uy) {
-  double l = T00;
+                                             double& uy, double l0) {
+  double l = l0;
   const double b2c2 = T0x * T0x + T0y * T0y;
   const double bce2 = 2.0 * T0x * T0y * Txy;
   const double e2 = Txy * Txy;
+  if (l != T00) {  // a start below T^00 must lie where p is increasing
+    const double pd = l + Txx, pf = l + Tyy;
+    if (!(fma(l - T00, pd + pf, fma(pd, pf, -e2) + b2c2) > 0.0)) l = T00;
+  }
   int it = 1;
   bool done = false;
   for (; it <= maxit; ++it) {

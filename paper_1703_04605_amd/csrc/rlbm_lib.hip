@@ -19,6 +19,7 @@
 
 #include "../../include/rlbm.h"
 #include "rlbm_device.h"
+#include "rlbm_mlp.h"
 #include "rlbm_stencil.h"
 #include "rlbm_tables.h"
 
@@ -84,15 +85,20 @@ struct Macro {
   unsigned flags;
 };
 
+// guess (eps0, ux0, uy0): starting point of the Landau solve; eps0 <= 0 means
+// none (Newton from T^00, fixed point from u = 0)
 __device__ __forceinline__ Macro macroscopic(TabPtr tb, double N0, double Nx, double Ny,
                                              double T00, double T0x, double T0y, double Txx, double Txy,
-                                             double Tyy, double tol, int maxit, int method) {
+                                             double Tyy, double tol, int maxit, int method, double eps0 = 0.0,
+                                             double ux0 = 0.0, double uy0 = 0.0) {
   Macro m;
   m.flags = 0;
-  m.ux = 0.0;
-  m.uy = 0.0;
+  const bool guess = eps0 > 0.0 && eps0 < T00 && ux0 * ux0 + uy0 * uy0 < 1.0;
+  m.ux = guess ? ux0 : 0.0;
+  m.uy = guess ? uy0 : 0.0;
   if (method == RLBM_LANDAU_NEWTON)
-    m.iters = landau_newton(T00, T0x, T0y, Txx, Txy, Tyy, 0.1 * sqrt(tol), maxit, m.eps, m.ux, m.uy);
+    m.iters = landau_newton(T00, T0x, T0y, Txx, Txy, Tyy, 0.1 * sqrt(tol), maxit, m.eps, m.ux, m.uy,
+                            guess ? eps0 : T00);
   else
     m.iters = landau_solve(T00, T0x, T0y, Txx, Txy, Tyy, tol, maxit, m.eps, m.ux, m.uy);
   if (m.iters > maxit) m.flags |= RLBM_H_LANDAU;
@@ -142,13 +148,135 @@ __device__ __forceinline__ void store_ghosts(S* __restrict__ q, const RlbmLayout
   }
 }
 
+
+// ------------------------------------------------------------------ learned guess
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ v4s pack4(float a, float b, float c, float d) {
+  v4s r;
+  r[0] = (short)to_bf16(a);
+  r[1] = (short)to_bf16(b);
+  r[2] = (short)to_bf16(c);
+  r[3] = (short)to_bf16(d);
+  return r;
+}
+
+__device__ __forceinline__ float silu_f(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+
+// The network evaluated for the 64 sites of a wave on the matrix cores
+// (32x32x8 bf16 products, float32 accumulation).  Each layer computes
+// H^T = W A^T, with units along M and sites along N (two tiles of 32 sites);
+// lane l then holds units 8 (r/4) + 4 (l/32) + r%4 of site l%32 in
+// accumulator register r, which is exactly the B operand layout of the next
+// layer, so activations never leave their lanes.  Returns, in every lane, the
+// standardised outputs of the lane's own site.  All 64 lanes must be active.
+__device__ __forceinline__ void mlp_wave(const RlbmStepArgs& a, const float xin[9], float out[3]) {
+  const int l = threadIdx.x & 63;
+  const int half = l >> 5;
+  const v4s* __restrict__ frag = (const v4s*)a.mlp_frag;
+  const v16f* __restrict__ bias = (const v16f*)a.mlp_bias;
+
+  // layer-1 B operands: inputs 8s + 4 half + i of site (l % 32) + 32 t
+  v4s bop[2][8];
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    float own[4], oth[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int ko = 8 * s + 4 * half + i, kt = 8 * s + 4 * (1 - half) + i;
+      own[i] = ko < 9 ? xin[ko] : 0.0f;
+      oth[i] = kt < 9 ? xin[kt] : 0.0f;
+    }
+    float sw[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) sw[i] = __shfl_xor(oth[i], 32);
+    // tile t = half: own site; tile 1 - half: the partner lane's site
+    const v4s pown = pack4(own[0], own[1], own[2], own[3]);
+    const v4s psw = pack4(sw[0], sw[1], sw[2], sw[3]);
+    bop[half ? 1 : 0][s] = pown;
+    bop[half ? 0 : 1][s] = psw;
+  }
+
+  // hidden layers
+  int ksteps = 2;
+#pragma unroll
+  for (int L = 0; L < 3; ++L) {
+    v4s nxt[2][8];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const v16f b0 = bias[(RLBM_MLP_BFOFF[L] + m) * 64 + l];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        v16f acc = b0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+          if (s < ksteps)
+            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(frag[(RLBM_MLP_FOFF[L] + m * RLBM_MLP_KSTEPS[L] + s) * 64 + l],
+                                                           bop[t][s], acc, 0, 0, 0);
+        // registers 4q..4q+3 of tile m are the k-step 4m + q operand of the next layer
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          nxt[t][4 * m + q] = pack4(silu_f(acc[4 * q]), silu_f(acc[4 * q + 1]), silu_f(acc[4 * q + 2]),
+                                    silu_f(acc[4 * q + 3]));
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int s = 0; s < 8; ++s) bop[t][s] = nxt[t][s];
+    ksteps = 8;
+  }
+
+  // output layer: one tile of 32 rows (3 used)
+  float res[2][3];
+  const v16f b3 = bias[RLBM_MLP_BFOFF[3] * 64 + l];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    v16f acc = b3;
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(frag[(RLBM_MLP_FOFF[3] + s) * 64 + l], bop[t][s], acc, 0, 0, 0);
+    res[t][0] = acc[0];
+    res[t][1] = acc[1];
+    res[t][2] = acc[2];
+  }
+  // rows 0..2 live in lanes 0..31: tile 0 is theirs, tile 1 belongs to lane + 32
+#pragma unroll
+  for (int o = 0; o < 3; ++o) {
+    const float other = __shfl_xor(res[1][o], 32);
+    out[o] = half ? other : res[0][o];
+  }
+}
+
+// standardised inputs of a site from its float64 moments
+__device__ __forceinline__ void mlp_inputs(const RlbmStepArgs& a, const double md[9], float xin[9]) {
+  const double inv = 1.0 / md[0];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) xin[i] = ((float)(md[i] * inv) - a.mlp_norm[i]) * a.mlp_norm[9 + i];
+}
+
+__device__ __forceinline__ void mlp_destandardise(const RlbmStepArgs& a, double n0, const float out[3], double& eps,
+                                                  double& ux, double& uy) {
+  eps = ((double)out[0] * a.mlp_norm[21] + a.mlp_norm[18]) * n0;
+  ux = (double)out[1] * a.mlp_norm[22] + a.mlp_norm[19];
+  uy = (double)out[2] * a.mlp_norm[23] + a.mlp_norm[20];
+}
+
 // ------------------------------------------------------------------ step
 
 // Waves per SIMD requested from the register allocator: enough to overlap one
 // wave's arithmetic with other waves' loads, while the class values of the
 // largest stencils still fit in registers.
-constexpr int step_waves(int qn, int p) {
-  return p == RLBM_FP64 ? (qn <= 48 ? 3 : qn <= 80 ? 2 : 1) : (qn <= 48 ? 4 : qn <= 80 ? 3 : 2);
+constexpr int step_waves(int qn, int p, bool g) {
+  return g ? (p == RLBM_FP64 ? (qn <= 24 ? 2 : 1) : (qn <= 24 ? 3 : 2))
+           : p == RLBM_FP64 ? (qn <= 48 ? 3 : qn <= 80 ? 2 : 1) : (qn <= 48 ? 4 : qn <= 80 ? 3 : 2);
 }
 
 // One time step for a block of kBlock consecutive sites of one row, for a
@@ -156,8 +284,8 @@ constexpr int step_waves(int qn, int p) {
 // populations stay in registers; the pull loop is unguarded so all pulls are
 // issued back to back (classes Q <= j < QN read class 0's source and have
 // all-zero table rows), the arithmetic loops skip them.
-template <int QN, int P>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves(QN, P))))
+template <int QN, int P, bool G>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves(QN, P, G))))
 k_step(RlbmStepArgs a) {
   using S = typename Traits<P>::S;
   using A = typename Traits<P>::A;
@@ -214,8 +342,15 @@ k_step(RlbmStepArgs a) {
 #pragma unroll
   for (int k = 0; k < 9; ++k) md[k] = (P == RLBM_FP64) ? (double)m[k] : tb->c.ref_mom[k] + (double)m[k];
 
+  double e0 = 0.0, ux0 = 0.0, uy0 = 0.0;
+  if constexpr (G) {
+    float xin[9], yo[3];
+    mlp_inputs(a, md, xin);
+    mlp_wave(a, xin, yo);
+    mlp_destandardise(a, md[0], yo, e0, ux0, uy0);
+  }
   Macro mac = macroscopic(tb, md[0], md[1], md[2], md[3], md[4], md[5], md[6], md[7], md[8], a.landau_tol,
-                          a.landau_maxit, a.landau_method);
+                          a.landau_maxit, a.landau_method, e0, ux0, uy0);
   const double tau = a.tau_mode == RLBM_TAU_CONST ? a.tau : tau_eta_over_s(a.tk1, a.tk2, mac.n, mac.T);
   double b[RLBM_NB];
   projections(tb, mac.T, mac.R, mac.gamma, mac.gamma * mac.ux, mac.gamma * mac.uy, b);
@@ -335,23 +470,62 @@ using StepFn = void (*)(RlbmStepArgs);
 // Class-count buckets: exact fits for the configured stencils (19: zeta = 1
 // in 1D, 39: G1..G6 in 2D, 44: zeta = 1 in 2D, 73: the 133-population stencil
 // in 2D) and padded buckets for any other stencil.
-template <int P>
+template <int P, bool G>
 StepFn step_kernel(int Q) {
-  if (Q <= 19) return k_step<19, P>;
-  if (Q <= 24) return k_step<24, P>;
-  if (Q <= 39) return k_step<39, P>;
-  if (Q <= 44) return k_step<44, P>;
-  if (Q <= 48) return k_step<48, P>;
-  if (Q <= 73) return k_step<73, P>;
-  if (Q <= 80) return k_step<80, P>;
-  return k_step<160, P>;
+  if (Q <= 19) return k_step<19, P, G>;
+  if (Q <= 24) return k_step<24, P, G>;
+  if (Q <= 39) return k_step<39, P, G>;
+  if (Q <= 44) return k_step<44, P, G>;
+  if (Q <= 48) return k_step<48, P, G>;
+  if (Q <= 73) return k_step<73, P, G>;
+  if (Q <= 80) return k_step<80, P, G>;
+  return k_step<160, P, G>;
 }
 
-StepFn select_step(int prec, int Q) {
+// The learned-guess kernels are built for float32 storage, the path the
+// guess is meant for.
+StepFn select_step(int prec, int Q, bool guess) {
+  if (guess && prec == RLBM_FP32_DEV) return step_kernel<RLBM_FP32_DEV, true>(Q);
   switch (prec) {
-    case RLBM_FP64: return step_kernel<RLBM_FP64>(Q);
-    case RLBM_FP32_DEV: return step_kernel<RLBM_FP32_DEV>(Q);
-    default: return step_kernel<RLBM_FP16_DEV>(Q);
+    case RLBM_FP64: return step_kernel<RLBM_FP64, false>(Q);
+    case RLBM_FP32_DEV: return step_kernel<RLBM_FP32_DEV, false>(Q);
+    default: return step_kernel<RLBM_FP16_DEV, false>(Q);
+  }
+}
+
+// Diagnostic: the network's guess (eps, ux, uy) for the current state, from the
+// same in-kernel inference as the step (one wave per 64 consecutive sites).
+__global__ void __launch_bounds__(kBlock) k_guess(RlbmStepArgs a, float* __restrict__ out) {
+  const TabPtr tb = as_tab(a.tab);
+  const RlbmLayout& L = a.L;
+  const long long S2 = (long long)L.nx * L.ny;
+  const long long site0 = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long site = site0 < S2 ? site0 : S2 - 1;
+  const int y = (int)(site / L.nx), x = (int)(site - (long long)y * L.nx);
+  double md[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < tb->c.Q; ++j) {
+    const int sx = a.shift ? x - tb->nx[j] : x, sy = a.shift ? y - tb->ny[j] : y;
+    const long long idx = (long long)j * L.plane + (long long)(sy + L.GY) * L.W + sx + L.GX;
+    double f;
+    if (tb->c.precision == RLBM_FP64) f = ((const double*)a.src)[idx];
+    else if (tb->c.precision == RLBM_FP32_DEV) f = ((const float*)a.src)[idx];
+    else f = (double)((float)((const _Float16*)a.src)[idx] * tb->scale[j]);
+    const double p0 = tb->p0[j], px = tb->px[j], py = tb->py[j];
+    md[0] += f * p0; md[1] += f * px; md[2] += f * py;
+    md[3] += f * p0 * p0; md[4] += f * p0 * px; md[5] += f * p0 * py;
+    md[6] += f * px * px; md[7] += f * px * py; md[8] += f * py * py;
+  }
+  if (tb->c.precision != RLBM_FP64)
+    for (int k = 0; k < 9; ++k) md[k] += tb->c.ref_mom[k];
+  float xin[9], yo[3];
+  mlp_inputs(a, md, xin);
+  mlp_wave(a, xin, yo);
+  double e, ux, uy;
+  mlp_destandardise(a, md[0], yo, e, ux, uy);
+  if (site0 < S2) {
+    out[site0] = (float)e;
+    out[S2 + site0] = (float)ux;
+    out[2 * S2 + site0] = (float)uy;
   }
 }
 
@@ -378,6 +552,7 @@ struct rlbm_ctx {
   int* d_offs = nullptr;  // [0, QMAX): local read offsets, [QMAX, 2 QMAX): pull offsets
   int nblocks = 0, blocks_x = 0;
   double tk1 = 0, tk2 = 0;
+  const rlbm_mlp* guess = nullptr;
   char err[512] = {0};
 };
 
@@ -556,7 +731,14 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   a.landau_method = c->lat.landau_method;
   a.tab = c->d_tab;
   a.slots = c->d_slots;
-  StepFn fn = select_step(c->h_tab->c.precision, c->h_tab->c.Q);
+  const bool g = c->guess != nullptr && c->h_tab->c.precision == RLBM_FP32_DEV;
+  if (g) {
+    a.mlp_frag = c->guess->frag;
+    a.mlp_bias = c->guess->biasfrag;
+    for (int i = 0; i < 24; ++i) a.mlp_norm[i] = c->guess->h_norm[i];
+    for (int i = 0; i < 9; ++i) a.mlp_norm[9 + i] = 1.0f / c->guess->h_norm[9 + i];
+  }
+  StepFn fn = select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
   for (int i = 0; i < nsteps; ++i) {
     a.src = c->buf[c->cur];
     a.dst = c->buf[1 - c->cur];
@@ -645,3 +827,31 @@ extern "C" int rlbm_load_state(rlbm_ctx* c, const void* src, size_t bytes, long 
 }
 
 extern "C" const char* rlbm_last_error(const rlbm_ctx* c) { return c ? c->err : rlbm_global_error(); }
+
+extern "C" int rlbm_set_landau_guess(rlbm_ctx* c, const rlbm_mlp* m) {
+  if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
+  if (m && c->h_tab->c.precision != RLBM_FP32_DEV)
+    return fail(c, RLBM_EINVAL, "the learned guess is available for float32 deviation storage");
+  c->guess = m;
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_landau_guess_fields(rlbm_ctx* c, float* out, void* stream) {
+  if (!c || !out) return fail(c, RLBM_EINVAL, "NULL argument");
+  if (!c->have_fields || !c->guess) return fail(c, RLBM_ESTATE, "no fields or no network");
+  RlbmStepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.src = c->buf[c->cur];
+  a.L = c->L;
+  a.shift = c->shifted;
+  a.tab = c->d_tab;
+  a.mlp_frag = c->guess->frag;
+  a.mlp_bias = c->guess->biasfrag;
+  for (int i = 0; i < 24; ++i) a.mlp_norm[i] = c->guess->h_norm[i];
+  for (int i = 0; i < 9; ++i) a.mlp_norm[9 + i] = 1.0f / c->guess->h_norm[9 + i];
+  long long sites = (long long)c->L.nx * c->L.ny;
+  hipLaunchKernelGGL(k_guess, dim3((unsigned)((sites + kBlock - 1) / kBlock)), dim3(kBlock), 0, (hipStream_t)stream,
+                     a, out);
+  HIPCHECK(c, hipGetLastError());
+  return RLBM_OK;
+}

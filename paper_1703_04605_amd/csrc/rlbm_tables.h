@@ -101,6 +101,10 @@ struct RlbmStepArgs {
   int landau_method;   // RLBM_LANDAU_*
   const RlbmTable* tab;
   RlbmSlot* slots;     // one per block (logical index)
+  // learned Landau guess (kernels with the guess only)
+  const unsigned short* mlp_frag;
+  const float* mlp_bias;
+  float mlp_norm[24];  // mx[9], 1/sx[9], my[3], sy[3]
 };
 
 struct RlbmMomArgs {

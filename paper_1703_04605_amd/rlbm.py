@@ -29,7 +29,9 @@ H_NAN, H_LANDAU, H_SUPERLUMINAL, H_RANGE, H_EOS = 1, 2, 4, 8, 16
 EXPORTS = ["rlbm_init_stencil", "rlbm_solve_stencil", "rlbm_class_table", "rlbm_destroy",
            "rlbm_population_bytes", "rlbm_init_fields", "rlbm_step", "rlbm_moments",
            "rlbm_get_health", "rlbm_step_count", "rlbm_save_state", "rlbm_load_state",
-           "rlbm_last_error", "rlbm_eos_temperature_host"]
+           "rlbm_last_error", "rlbm_eos_temperature_host", "rlbm_mlp_create", "rlbm_mlp_destroy",
+           "rlbm_mlp_train_step", "rlbm_mlp_predict", "rlbm_mlp_get_params", "rlbm_set_landau_guess",
+           "rlbm_landau_guess_fields"]
 
 
 class RlbmError(RuntimeError):
@@ -89,6 +91,14 @@ def lib():
                                   ctypes.POINTER(ctypes.c_int), vp]
     L.rlbm_load_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_longlong, ci, vp]
     L.rlbm_eos_temperature_host.argtypes = [cd, dp, ci, dp]
+    fp = ctypes.POINTER(ctypes.c_float)
+    L.rlbm_mlp_create.argtypes = [ctypes.POINTER(vp), fp, fp, ci]
+    L.rlbm_mlp_destroy.argtypes = [vp]
+    L.rlbm_mlp_train_step.argtypes = [vp, vp, vp, ci, ctypes.c_float, fp, vp]
+    L.rlbm_mlp_predict.argtypes = [vp, vp, ci, vp, vp]
+    L.rlbm_mlp_get_params.argtypes = [vp, fp, fp]
+    L.rlbm_set_landau_guess.argtypes = [vp, vp]
+    L.rlbm_landau_guess_fields.argtypes = [vp, vp, vp]
     L.rlbm_last_error.argtypes = [vp]
     L.rlbm_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -146,6 +156,60 @@ def eos_temperature_host(zeta, e):
     dp = ctypes.POINTER(ctypes.c_double)
     _check(lib().rlbm_eos_temperature_host(float(zeta), e.ctypes.data_as(dp), e.size, T.ctypes.data_as(dp)))
     return T
+
+
+MLP_NPARAM = 9155
+
+
+class MLP:
+    """The learned Landau-frame guess network on the current device.
+    params: 9155 float32 values (W1, b1, W2, b2, W3, b3, W4, b4); norm: 24
+    float32 values mx[9], sx[9], my[3], sy[3]."""
+
+    def __init__(self, params, norm, max_batch=8192):
+        import numpy as np
+        import torch
+        self.torch = torch
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        nrm = np.ascontiguousarray(norm, dtype=np.float32)
+        assert p.size == MLP_NPARAM and nrm.size == 24
+        fp = ctypes.POINTER(ctypes.c_float)
+        h = ctypes.c_void_p()
+        _check(lib().rlbm_mlp_create(ctypes.byref(h), p.ctypes.data_as(fp), nrm.ctypes.data_as(fp), int(max_batch)))
+        self.h = h
+        self.max_batch = max_batch
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().rlbm_mlp_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def train_step(self, raw9, target, lr):
+        """raw9 [B, 9], target [B, 3] (eps, ux, uy): CUDA float32; returns the loss."""
+        assert raw9.dtype == self.torch.float32 and target.dtype == self.torch.float32
+        loss = ctypes.c_float()
+        _check(lib().rlbm_mlp_train_step(self.h, raw9.data_ptr(), target.data_ptr(), raw9.shape[0], float(lr),
+                                         ctypes.byref(loss), self._stream()))
+        return loss.value
+
+    def predict(self, raw9):
+        out = self.torch.empty((raw9.shape[0], 3), dtype=self.torch.float32, device=raw9.device)
+        _check(lib().rlbm_mlp_predict(self.h, raw9.data_ptr(), raw9.shape[0], out.data_ptr(), self._stream()))
+        return out
+
+    def params(self):
+        import numpy as np
+        p = np.empty(MLP_NPARAM, dtype=np.float32)
+        g = np.empty(MLP_NPARAM, dtype=np.float32)
+        fp = ctypes.POINTER(ctypes.c_float)
+        _check(lib().rlbm_mlp_get_params(self.h, p.ctypes.data_as(fp), g.ctypes.data_as(fp)))
+        return p, g
 
 
 class Solver:
@@ -231,6 +295,17 @@ class Solver:
         if rc not in (RLBM_OK, RLBM_ENUMERIC):
             _check(rc, self.ctx)
         return {"flags": f.value, "iter_sum": s.value, "iter_max": m.value, "fatal": rc == RLBM_ENUMERIC}
+
+    def set_landau_guess(self, mlp):
+        """Start every Landau solve from the network's guess (None: plain start)."""
+        self._mlp = mlp
+        _check(lib().rlbm_set_landau_guess(self.ctx, mlp.h if mlp is not None else None), self.ctx)
+
+    def landau_guess_fields(self):
+        torch = self.torch
+        out = torch.empty((3, self.ny, self.nx), dtype=torch.float32, device=self.pop[0].device)
+        _check(lib().rlbm_landau_guess_fields(self.ctx, out.data_ptr(), self._stream()), self.ctx)
+        return out
 
     def step_count(self):
         return lib().rlbm_step_count(self.ctx)
