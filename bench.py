@@ -22,7 +22,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 ELEM = {"fp64": 8, "fp32": 4, "fp16": 2}
 STEP_KERNEL_SOURCES = ["paper_1703_04605_amd/csrc/rlbm_lib.hip", "paper_1703_04605_amd/csrc/rlbm_device.h",
-                       "paper_1703_04605_amd/csrc/rlbm_tables.h"]
+                       "paper_1703_04605_amd/csrc/rlbm_tables.h", "paper_1703_04605_amd/csrc/rlbm_mlp.h",
+                       "paper_1703_04605_amd/csrc/bessel_ratio_coeffs.h"]
 
 
 def kernel_source_hash():
@@ -45,11 +46,13 @@ def measured_traffic(precision, nx, ny):
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
-def time_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton"):
+def time_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton", guess=None):
     import torch
     from paper_1703_04605_amd import rlbm
     s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=2, precision=precision)
     s.init_fields(*fields, tau=tau, landau=landau)
+    if guess is not None:
+        s.set_landau_guess(guess)
     s.step(warmup)
     s.health(reset=True)
     stream = torch.cuda.current_stream()
@@ -64,6 +67,38 @@ def time_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton"):
     ms = e0.elapsed_time(e1)
     h = s.health()
     return s, ms, wall, h
+
+
+def train_guess(st, size=256, steps=400):
+    """The learned Landau guess, trained by the library's kernels on moments of
+    Taylor-Green and Kelvin-Helmholtz runs it produces itself."""
+    import torch
+    import workloads
+    from paper_1703_04605_amd import rlbm, learned_guess
+    from tests.helpers import to_dev
+    X, Y = [], []
+    for k, gen in enumerate((workloads.taylor_green(size, size, seed=11),
+                             workloads.kelvin_helmholtz(size, size, seed=12))):
+        s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=2, precision="fp32")
+        s.init_fields(*to_dev(gen), tau=1.0)
+        x, y = learned_guess.collect(s, steps=60, every=10, max_sites=32768, seed=k)
+        X.append(x)
+        Y.append(y)
+    X, Y = torch.cat(X), torch.cat(Y)
+    net = rlbm.MLP(learned_guess.init_params(seed=0), learned_guess.normalisation(X, Y), max_batch=4096)
+    losses = learned_guess.train(net, X, Y, steps=steps, batch=4096, lr=2e-3)
+    return net, losses[0], losses[-1]
+
+
+def calibration_copy(nbytes=1 << 28):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
 
 
 def cpu_baseline(st, nx, target_s=12.0):
@@ -100,6 +135,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16"])
     ap.add_argument("--no-compare", action="store_true", help="skip the other precision paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-guess", action="store_true", help="skip the learned-guess paths")
+    ap.add_argument("--calibration-copy", action="store_true", help="also run a 256 MiB device copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -114,6 +151,8 @@ def main():
     st = workloads.STENCILS[args.stencil]
     nx = ny = args.size
     fields = to_dev(workloads.taylor_green(nx, ny, seed=0))
+    if args.calibration_copy:
+        calibration_copy()
 
     s, ms, wall, h = time_path(st, fields, args.precision, args.steps, args.warmup)
     q = s.info["q"]
@@ -152,6 +191,27 @@ def main():
             del s2
         if "fp64" in paths:
             paths["speedup_vs_fp64"] = mlups / paths["fp64"]["mlups"]
+    if not args.no_guess:
+        net, l0, l1 = train_guess(st)
+        for key, landau in (("fp32_guess", "newton"), ("fp32_guess_fixed_point", "fixed_point")):
+            s2, ms2, _, h2 = time_path(st, fields, "fp32", args.steps, args.warmup, landau=landau, guess=net)
+            m2 = sites * args.steps / (ms2 * 1e-3) / 1e6
+            ab = 2 * q * 4 * sites / (ms2 / args.steps * 1e-3) / 1e9
+            o2 = {k: v.cpu().numpy() for k, v in s2.moments().items()}
+            paths[key] = {"mlups": m2, "ms_per_step": ms2 / args.steps, "hbm_frac": ab / HBM_PEAK_GBS,
+                          "landau_iter_mean": h2["iter_sum"] / (sites * args.steps),
+                          "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"]}
+            ref_key = "fp32" if landau == "newton" else "fp32_fixed_point"
+            if ref_key == args.precision or ref_key in paths:
+                paths[key]["speedup_vs_unguided"] = m2 / paths[ref_key]["mlups"]
+            if landau == "newton" and args.precision == "fp32":
+                paths[key]["max_rel_err_vs_unguided"] = {
+                    k: float(np.abs(o2[k] - out_hp[k]).max() / np.abs(out_hp[k]).max())
+                    for k in ("n", "eps", "T", "P", "ux", "uy")}
+            if "fp64" in paths:
+                paths[key]["speedup_vs_fp64"] = m2 / paths["fp64"]["mlups"]
+            del s2
+        paths["guess_training_loss"] = {"first": l0, "last": l1}
 
     cpu = None if args.no_cpu_baseline else cpu_baseline(st, nx)
     res = {
