@@ -90,6 +90,32 @@ def train_guess(st, size=256, steps=400):
     return net, losses[0], losses[-1]
 
 
+def time_batched(steps=500):
+    """64 independent quasi-1D shock tubes (lengths 256..4096, mbar snapped to
+    0.36/1/5/10, eta/s 0.05..0.5, pressure ratios 2..50), 500 steps in one
+    persistent launch, float32 deviation storage."""
+    import torch
+    import workloads
+    from paper_1703_04605_amd import rlbm
+    problems, fields = workloads.batched_riemann(nprob=64, seed=0)
+    names = sorted({p["stencil_name"] for p in problems})
+    stencils = [rlbm.Solver(workloads.STENCILS[nm]["bases"], workloads.STENCILS[nm]["zeta"],
+                            workloads.STENCILS[nm]["v0"], dim=1, precision="fp32") for nm in names]
+    b = rlbm.Batch(stencils, [dict(p, stencil=names.index(p["stencil_name"])) for p in problems])
+    b.init(*[torch.tensor(a, dtype=torch.float64, device="cuda") for a in fields])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    h = b.health()
+    return {"mlups": b.sites * steps / (ms * 1e-3) / 1e6, "ms": ms, "sites": int(b.sites), "steps": steps,
+            "launches": 1, "landau_iter_mean": h["iter_sum"] / (b.sites * steps), "health_flags": h["flags"],
+            "note": "one workgroup per problem; cache-resident (2 x 9.9 MB of populations), not HBM-bound"}
+
+
 def calibration_copy(nbytes=1 << 28):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -137,6 +163,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-guess", action="store_true", help="skip the learned-guess paths")
     ap.add_argument("--calibration-copy", action="store_true", help="also run a 256 MiB device copy")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-problem workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -213,6 +240,8 @@ def main():
             del s2
         paths["guess_training_loss"] = {"first": l0, "last": l1}
 
+    if not args.no_batched and not args.no_compare:
+        paths["batched_riemann_64x500"] = time_batched()
     cpu = None if args.no_cpu_baseline else cpu_baseline(st, nx)
     res = {
         "metric": "MLUPS (site updates per second / 1e6) of the RLBM time step",

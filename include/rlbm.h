@@ -256,6 +256,43 @@ int rlbm_set_landau_guess(rlbm_ctx* ctx, const rlbm_mlp* m);
  * eps, u_x, u_y.  RLBM_ESTATE without fields or network. */
 int rlbm_landau_guess_fields(rlbm_ctx* ctx, float* out, void* stream);
 
+/*
+ * Batched 1D problems in one persistent launch.  Each problem is an Nx x 1
+ * lattice with outflow ends, float32 deviation storage and tau from eta/s
+ * (rlbm_lattice_desc's RLBM_TAU_ETA_OVER_S rule), using one of the given
+ * stencil contexts (rlbm_init_stencil with dim 1, RLBM_FP32_DEV, at most 24
+ * classes; they must outlive the batch).  One workgroup advances one problem
+ * through all steps of a call, with a workgroup barrier between steps.
+ */
+typedef struct {
+  int nx;                 /* sites */
+  int stencil;            /* index into the stencils of rlbm_batch_create */
+  double eta_over_s, T_R_GeV, n_unit_fm3, dx_fm;
+} rlbm_problem;
+typedef struct rlbm_batch rlbm_batch;
+int rlbm_batch_create(rlbm_batch** out, int nstencils, rlbm_ctx* const* stencils, int nprob, const rlbm_problem* probs,
+                      double landau_tol, int landau_maxit);
+int rlbm_batch_destroy(rlbm_batch* b);
+/* bytes of one population buffer; total sites (sum of nx) */
+size_t rlbm_batch_population_bytes(const rlbm_batch* b);
+long long rlbm_batch_sites(const rlbm_batch* b);
+/* f = f^eq(n, T, u_x) from device float64 fields concatenated over the
+ * problems (sum of nx each); popA, popB: caller-owned device buffers. */
+int rlbm_batch_init(rlbm_batch* b, const double* n, const double* T, const double* ux, void* popA, void* popB,
+                    size_t bytes, void* stream);
+/* nsteps steps of every problem in one launch.  samples (device, nullable):
+ * at every step t (0-based within the call) with t % sample_every == 0, the
+ * pre-collision state of every site as 12 floats (N^0, N^x, N^y, T^00, T^0x,
+ * T^0y, T^xx, T^xy, T^yy, eps, u_x, u_y): training pairs for the learned
+ * guess; layout [t / sample_every][site][12]. */
+int rlbm_batch_step_persistent(rlbm_batch* b, int nsteps, int sample_every, float* samples, void* stream);
+/* pre-collision fields (device float64, concatenated; any may be NULL) */
+int rlbm_batch_moments(rlbm_batch* b, double* n, double* eps, double* T, double* P, double* ux, void* stream);
+/* OR of the health flags and Landau iteration statistics of all problems
+ * (synchronises stream); RLBM_ENUMERIC if a fatal flag is set. */
+int rlbm_batch_get_health(rlbm_batch* b, unsigned* flags, unsigned long long* iter_sum, unsigned* iter_max,
+                          void* stream);
+
 /* Last error message of ctx (or of the last failed context-less call when
  * ctx is NULL).  The string is owned by the library. */
 const char* rlbm_last_error(const rlbm_ctx* ctx);

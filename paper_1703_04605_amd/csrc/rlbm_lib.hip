@@ -855,3 +855,368 @@ extern "C" int rlbm_landau_guess_fields(rlbm_ctx* c, float* out, void* stream) {
   HIPCHECK(c, hipGetLastError());
   return RLBM_OK;
 }
+
+// ====================================================================== batch
+//
+// Many independent 1D problems (float32 deviation storage, outflow ends, tau
+// from eta/s), each with its own stencil, advanced for many steps in ONE
+// launch: one workgroup owns one problem and loops over its sites; a
+// workgroup barrier separates the steps (the ping-pong buffers of a problem
+// are touched by its workgroup only).
+
+namespace rlbm {
+
+constexpr int kBatchBlock = 512;
+constexpr int kBatchQ = 24;  // classes of a 1D stencil
+
+struct RlbmBatchProblem {
+  long long base;  // element offset of plane 0
+  int W;           // plane length: L + 2 S, rounded up to 64
+  int L, S;        // sites, ghost width (max |n_x|)
+  int table;       // stencil index
+  long long site_off;  // offset of the problem's sites in concatenated field arrays
+  double tk1, tk2;     // tau = 1/2 + tk1 (4 - ln(tk2 n / T^3)) / T
+};
+
+struct RlbmBatchArgs {
+  const void* src;
+  void* dst;
+  int shift;
+  int nsteps;
+  int sample_every;
+  float* samples;       // [nsamples][total_sites][12] or NULL
+  long long total_sites;
+  const RlbmBatchProblem* probs;
+  const RlbmTable* const* tables;
+  double landau_tol;
+  int landau_maxit;
+  RlbmSlot* slots;      // one per problem
+};
+
+__device__ __forceinline__ void batch_site(const RlbmBatchArgs& a, const RlbmBatchProblem& pr, TabPtr tb,
+                                           const float* __restrict__ src, float* __restrict__ dst, int x, int shift,
+                                           float* __restrict__ sample, unsigned& flags, unsigned& iters) {
+  const int Q = tb->c.Q;
+  float f[kBatchQ];
+#pragma unroll
+  for (int j = 0; j < kBatchQ; ++j)
+    f[j] = j < Q ? src[pr.base + (long long)j * pr.W + x + pr.S - (shift ? tb->nx[j] : 0)] : 0.0f;
+  float m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < kBatchQ; ++j) {
+    if (j < Q) {
+      const float p0 = tb->rowf[j][RLBM_R_P0], px = tb->rowf[j][RLBM_R_PX], py = tb->rowf[j][RLBM_R_PY];
+      const float a0 = f[j] * p0, ax = f[j] * px, ay = f[j] * py;
+      m[0] += a0; m[1] += ax; m[2] += ay;
+      m[3] = fmaf(a0, p0, m[3]); m[4] = fmaf(a0, px, m[4]); m[5] = fmaf(a0, py, m[5]);
+      m[6] = fmaf(ax, px, m[6]); m[7] = fmaf(ax, py, m[7]); m[8] = fmaf(ay, py, m[8]);
+    }
+  }
+  double md[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) md[k] = tb->c.ref_mom[k] + (double)m[k];
+  Macro mac = macroscopic(tb, md[0], md[1], md[2], md[3], md[4], md[5], md[6], md[7], md[8], a.landau_tol,
+                          a.landau_maxit, RLBM_LANDAU_NEWTON);
+  flags |= mac.flags;
+  iters = (unsigned)mac.iters;
+  if (sample) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) sample[k] = (float)md[k];
+    sample[9] = (float)mac.eps;
+    sample[10] = (float)mac.ux;
+    sample[11] = (float)mac.uy;
+  }
+  const double tau = tau_eta_over_s(pr.tk1, pr.tk2, mac.n, mac.T);
+  double b[RLBM_NB];
+  projections(tb, mac.T, mac.R, mac.gamma, mac.gamma * mac.ux, mac.gamma * mac.uy, b);
+  const double w0 = mac.gamma / tau;
+  const float W0 = (float)w0, WX = (float)(-w0 * tb->c.v0 * mac.ux), WY = (float)(-w0 * tb->c.v0 * mac.uy);
+  float nb[RLBM_NB];
+#pragma unroll
+  for (int k = 0; k < RLBM_NB; ++k) nb[k] = (float)(mac.n * b[k] - tb->c.nb_ref[k]);
+#pragma unroll
+  for (int j = 0; j < kBatchQ; ++j) {
+    if (j < Q) {
+      const auto* r = tb->rowf[j];
+      float feq = nb[0] * r[0];
+#pragma unroll
+      for (int k = 1; k < RLBM_NB; ++k) feq = fmaf(nb[k], r[k], feq);
+      const float om = fmaf(WY, r[RLBM_R_NY], fmaf(WX, r[RLBM_R_NX], W0));
+      const float out = fmaf(-om, f[j] - feq, f[j]);
+      float* q = dst + pr.base + (long long)j * pr.W + pr.S;
+      q[x] = out;
+      // outflow ghosts: the end sites stand for every site beyond them
+      if (x == 0)
+        for (int g = 1; g <= pr.S; ++g) q[-g] = out;
+      if (x == pr.L - 1)
+        for (int g = 1; g <= pr.S; ++g) q[pr.L - 1 + g] = out;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBatchBlock) k_batch(RlbmBatchArgs a) {
+  const RlbmBatchProblem pr = a.probs[blockIdx.x];
+  const TabPtr tb = as_tab(a.tables[pr.table]);
+  const float* src = (const float*)a.src;
+  float* dst = (float*)a.dst;
+  int shift = a.shift;
+  unsigned flags = 0, imax = 0, isum = 0;
+  for (int t = 0; t < a.nsteps; ++t) {
+    const bool sampling = a.samples != nullptr && (t % a.sample_every) == 0;
+    float* srow = sampling ? a.samples + ((long long)(t / a.sample_every) * a.total_sites + pr.site_off) * 12 : nullptr;
+    for (int x0 = 0; x0 < pr.L; x0 += kBatchBlock) {
+      const int x = x0 + (int)threadIdx.x;
+      if (x < pr.L) {
+        unsigned it = 0;
+        batch_site(a, pr, tb, src, dst, x, shift, srow ? srow + (long long)x * 12 : nullptr, flags, it);
+        imax = max(imax, it);
+        isum += it;
+      }
+    }
+    __syncthreads();  // every site of this step is written before the next step reads it
+    const float* tmp = src;
+    src = dst;
+    dst = (float*)tmp;
+    shift = 1;
+  }
+  // per-problem statistics (thread-level values reduced over the block)
+  __shared__ unsigned s_f[kBatchBlock / 64], s_m[kBatchBlock / 64], s_s[kBatchBlock / 64];
+  for (int off = 32; off > 0; off >>= 1) {
+    flags |= __shfl_xor(flags, off);
+    imax = max(imax, (unsigned)__shfl_xor(imax, off));
+    isum += __shfl_xor(isum, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_f[threadIdx.x >> 6] = flags;
+    s_m[threadIdx.x >> 6] = imax;
+    s_s[threadIdx.x >> 6] = isum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    RlbmSlot s = a.slots[blockIdx.x];
+    for (int i = 0; i < kBatchBlock / 64; ++i) {
+      s.flags |= s_f[i];
+      s.iter_max = max(s.iter_max, s_m[i]);
+      s.iter_sum += s_s[i];
+    }
+    a.slots[blockIdx.x] = s;
+  }
+}
+
+// f = f^eq(n, T, u) of every problem (fields concatenated over the problems)
+__global__ void __launch_bounds__(256) k_batch_init(const RlbmBatchProblem* probs, const RlbmTable* const* tables,
+                                                  const double* __restrict__ n, const double* __restrict__ T,
+                                                  const double* __restrict__ ux, float* __restrict__ dst) {
+  const RlbmBatchProblem pr = probs[blockIdx.x];
+  const TabPtr tb = as_tab(tables[pr.table]);
+  for (int x = threadIdx.x; x < pr.L; x += 256) {
+    const long long i = pr.site_off + x;
+    const double u = ux[i];
+    const double g = 1.0 / sqrt(1.0 - u * u);
+    double b[RLBM_NB];
+    projections(tb, T[i], k1k2_ratio(tb->c.zeta / T[i]), g, g * u, 0.0, b);
+    for (int j = 0; j < tb->c.Q; ++j) {
+      double fe = 0.0;
+      for (int k = 0; k < RLBM_NB; ++k) fe = fma(n[i] * b[k] - tb->c.nb_ref[k], tb->M[k][j], fe);
+      dst[pr.base + (long long)j * pr.W + pr.S + x] = (float)fe;
+    }
+  }
+}
+
+// pre-collision fields of every problem
+__global__ void __launch_bounds__(256) k_batch_moments(const RlbmBatchProblem* probs, const RlbmTable* const* tables,
+                                                     const float* __restrict__ src, int shift, double tol, int maxit,
+                                                     double* n, double* eps, double* T, double* P, double* ux) {
+  const RlbmBatchProblem pr = probs[blockIdx.x];
+  const TabPtr tb = as_tab(tables[pr.table]);
+  for (int x = threadIdx.x; x < pr.L; x += 256) {
+    double m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    for (int j = 0; j < tb->c.Q; ++j) {
+      const double f = src[pr.base + (long long)j * pr.W + x + pr.S - (shift ? tb->nx[j] : 0)];
+      const double p0 = tb->p0[j], px = tb->px[j];
+      m[0] += f * p0; m[1] += f * px; m[3] += f * p0 * p0; m[4] += f * p0 * px; m[6] += f * px * px;
+    }
+    for (int k = 0; k < 9; ++k) m[k] += tb->c.ref_mom[k];
+    Macro mac = macroscopic(tb, m[0], m[1], m[2], m[3], m[4], m[5], m[6], m[7], m[8], tol, maxit,
+                            RLBM_LANDAU_NEWTON);
+    const long long i = pr.site_off + x;
+    if (n) n[i] = mac.n;
+    if (eps) eps[i] = mac.eps;
+    if (T) T[i] = mac.T;
+    if (P) P[i] = mac.P;
+    if (ux) ux[i] = mac.ux;
+  }
+}
+
+}  // namespace rlbm
+
+struct rlbm_batch {
+  int nprob = 0;
+  std::vector<RlbmBatchProblem> h_probs;
+  RlbmBatchProblem* d_probs = nullptr;
+  const RlbmTable** d_tables = nullptr;
+  long long total_sites = 0, total_elems = 0;
+  void* buf[2] = {nullptr, nullptr};
+  int cur = 0, shifted = 0;
+  long long steps = 0;
+  bool have_fields = false;
+  RlbmSlot* d_slots = nullptr;
+  double landau_tol = 1e-10;
+  int landau_maxit = 200;
+};
+
+static int bfail(const char* msg) {
+  rlbm_set_global_error(msg);
+  return RLBM_EINVAL;
+}
+
+#define BHIP(call)                                                                     \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      char b_[256];                                                                    \
+      snprintf(b_, sizeof(b_), "HIP error: %s", hipGetErrorString(e_));                \
+      rlbm_set_global_error(b_);                                                       \
+      return RLBM_EHIP;                                                                \
+    }                                                                                  \
+  } while (0)
+
+extern "C" int rlbm_batch_create(rlbm_batch** out, int nstencils, rlbm_ctx* const* stencils, int nprob,
+                                 const rlbm_problem* probs, double landau_tol, int landau_maxit) {
+  if (!out || nstencils <= 0 || !stencils || nprob <= 0 || !probs) return bfail("rlbm_batch_create: invalid argument");
+  *out = nullptr;
+  for (int s = 0; s < nstencils; ++s) {
+    const RlbmConsts& k = stencils[s]->h_tab->c;
+    if (k.dim != 1 || k.precision != RLBM_FP32_DEV || k.Q > kBatchQ)
+      return bfail("rlbm_batch_create: stencils must be 1D, float32 deviation, at most 24 classes");
+  }
+  rlbm_batch* b = new rlbm_batch();
+  b->nprob = nprob;
+  b->landau_tol = landau_tol > 0 ? landau_tol : 1e-10;
+  b->landau_maxit = landau_maxit > 0 ? landau_maxit : 200;
+  long long elems = 0, sites = 0;
+  for (int p = 0; p < nprob; ++p) {
+    const rlbm_problem& q = probs[p];
+    if (q.nx <= 0 || q.stencil < 0 || q.stencil >= nstencils || !(q.eta_over_s > 0) || !(q.T_R_GeV > 0) ||
+        !(q.n_unit_fm3 > 0) || !(q.dx_fm > 0)) {
+      delete b;
+      return bfail("rlbm_batch_create: invalid problem");
+    }
+    const rlbm_ctx* c = stencils[q.stencil];
+    const RlbmConsts& k = c->h_tab->c;
+    RlbmBatchProblem pr;
+    pr.S = k.sx_max;
+    pr.L = q.nx;
+    pr.W = (q.nx + 2 * pr.S + 63) / 64 * 64;
+    pr.base = elems;
+    pr.table = q.stencil;
+    pr.site_off = sites;
+    pr.tk1 = 1.5 * q.eta_over_s * kHbarC * k.v0 / (q.dx_fm * q.T_R_GeV);
+    pr.tk2 = q.n_unit_fm3 * M_PI * M_PI * kHbarC * kHbarC * kHbarC / (16.0 * q.T_R_GeV * q.T_R_GeV * q.T_R_GeV);
+    elems += (long long)k.Q * pr.W;
+    sites += q.nx;
+    b->h_probs.push_back(pr);
+  }
+  b->total_sites = sites;
+  b->total_elems = elems;
+  std::vector<const RlbmTable*> tabs(nstencils);
+  for (int s = 0; s < nstencils; ++s) tabs[s] = stencils[s]->d_tab;
+  if (hipMalloc((void**)&b->d_probs, sizeof(RlbmBatchProblem) * nprob) != hipSuccess ||
+      hipMalloc((void**)&b->d_tables, sizeof(RlbmTable*) * nstencils) != hipSuccess ||
+      hipMalloc((void**)&b->d_slots, sizeof(RlbmSlot) * nprob) != hipSuccess) {
+    rlbm_batch_destroy(b);
+    return bfail("rlbm_batch_create: device allocation failed");
+  }
+  BHIP(hipMemcpy(b->d_probs, b->h_probs.data(), sizeof(RlbmBatchProblem) * nprob, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(b->d_tables, tabs.data(), sizeof(RlbmTable*) * nstencils, hipMemcpyHostToDevice));
+  BHIP(hipMemset(b->d_slots, 0, sizeof(RlbmSlot) * nprob));
+  *out = b;
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_batch_destroy(rlbm_batch* b) {
+  if (!b) return RLBM_OK;
+  (void)hipDeviceSynchronize();
+  if (b->d_probs) (void)hipFree(b->d_probs);
+  if (b->d_tables) (void)hipFree((void*)b->d_tables);
+  if (b->d_slots) (void)hipFree(b->d_slots);
+  delete b;
+  return RLBM_OK;
+}
+
+extern "C" size_t rlbm_batch_population_bytes(const rlbm_batch* b) {
+  return b ? (size_t)b->total_elems * sizeof(float) : 0;
+}
+
+extern "C" long long rlbm_batch_sites(const rlbm_batch* b) { return b ? b->total_sites : -1; }
+
+extern "C" int rlbm_batch_init(rlbm_batch* b, const double* n, const double* T, const double* ux, void* popA,
+                               void* popB, size_t bytes, void* stream) {
+  if (!b || !n || !T || !ux || !popA || !popB || popA == popB) return bfail("rlbm_batch_init: invalid argument");
+  if (bytes < rlbm_batch_population_bytes(b)) return bfail("rlbm_batch_init: buffers too small");
+  b->buf[0] = popA;
+  b->buf[1] = popB;
+  b->cur = 0;
+  b->shifted = 0;
+  b->steps = 0;
+  hipStream_t s = (hipStream_t)stream;
+  BHIP(hipMemsetAsync(b->d_slots, 0, sizeof(RlbmSlot) * b->nprob, s));
+  hipLaunchKernelGGL(k_batch_init, dim3(b->nprob), dim3(256), 0, s, b->d_probs, b->d_tables, n, T, ux,
+                     (float*)popA);
+  BHIP(hipGetLastError());
+  b->have_fields = true;
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_batch_step_persistent(rlbm_batch* b, int nsteps, int sample_every, float* samples, void* stream) {
+  if (!b || !b->have_fields) return bfail("rlbm_batch_step_persistent: no fields");
+  if (nsteps < 0 || (samples && sample_every <= 0)) return bfail("rlbm_batch_step_persistent: invalid argument");
+  if (nsteps == 0) return RLBM_OK;
+  RlbmBatchArgs a;
+  a.src = b->buf[b->cur];
+  a.dst = b->buf[1 - b->cur];
+  a.shift = b->shifted;
+  a.nsteps = nsteps;
+  a.sample_every = sample_every > 0 ? sample_every : 1;
+  a.samples = samples;
+  a.total_sites = b->total_sites;
+  a.probs = b->d_probs;
+  a.tables = b->d_tables;
+  a.landau_tol = b->landau_tol;
+  a.landau_maxit = b->landau_maxit;
+  a.slots = b->d_slots;
+  hipLaunchKernelGGL(k_batch, dim3(b->nprob), dim3(kBatchBlock), 0, (hipStream_t)stream, a);
+  BHIP(hipGetLastError());
+  if (nsteps % 2) b->cur ^= 1;
+  b->shifted = 1;
+  b->steps += nsteps;
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_batch_moments(rlbm_batch* b, double* n, double* eps, double* T, double* P, double* ux,
+                                  void* stream) {
+  if (!b || !b->have_fields) return bfail("rlbm_batch_moments: no fields");
+  hipLaunchKernelGGL(k_batch_moments, dim3(b->nprob), dim3(256), 0, (hipStream_t)stream, b->d_probs, b->d_tables,
+                     (const float*)b->buf[b->cur], b->shifted, b->landau_tol, b->landau_maxit, n, eps, T, P, ux);
+  BHIP(hipGetLastError());
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_batch_get_health(rlbm_batch* b, unsigned* flags, unsigned long long* iter_sum,
+                                     unsigned* iter_max, void* stream) {
+  if (!b) return bfail("rlbm_batch_get_health: NULL");
+  BHIP(hipStreamSynchronize((hipStream_t)stream));
+  std::vector<RlbmSlot> h(b->nprob);
+  BHIP(hipMemcpy(h.data(), b->d_slots, sizeof(RlbmSlot) * b->nprob, hipMemcpyDeviceToHost));
+  unsigned f = 0, mx = 0;
+  unsigned long long sm = 0;
+  for (auto& x : h) {
+    f |= x.flags;
+    mx = mx > x.iter_max ? mx : x.iter_max;
+    sm += x.iter_sum;
+  }
+  if (flags) *flags = f;
+  if (iter_sum) *iter_sum = sm;
+  if (iter_max) *iter_max = mx;
+  return (f & RLBM_H_FATAL) ? RLBM_ENUMERIC : RLBM_OK;
+}

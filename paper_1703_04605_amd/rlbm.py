@@ -31,7 +31,9 @@ EXPORTS = ["rlbm_init_stencil", "rlbm_solve_stencil", "rlbm_class_table", "rlbm_
            "rlbm_get_health", "rlbm_step_count", "rlbm_save_state", "rlbm_load_state",
            "rlbm_last_error", "rlbm_eos_temperature_host", "rlbm_mlp_create", "rlbm_mlp_destroy",
            "rlbm_mlp_train_step", "rlbm_mlp_predict", "rlbm_mlp_get_params", "rlbm_set_landau_guess",
-           "rlbm_landau_guess_fields"]
+           "rlbm_landau_guess_fields", "rlbm_batch_create", "rlbm_batch_destroy", "rlbm_batch_population_bytes",
+           "rlbm_batch_sites", "rlbm_batch_init", "rlbm_batch_step_persistent", "rlbm_batch_moments",
+           "rlbm_batch_get_health"]
 
 
 class RlbmError(RuntimeError):
@@ -59,6 +61,11 @@ class LatticeDesc(ctypes.Structure):
                 ("tau_mode", ctypes.c_int), ("tau", ctypes.c_double), ("eta_over_s", ctypes.c_double),
                 ("T_R_GeV", ctypes.c_double), ("n_unit_fm3", ctypes.c_double), ("dx_fm", ctypes.c_double),
                 ("landau_tol", ctypes.c_double), ("landau_maxit", ctypes.c_int), ("landau_method", ctypes.c_int)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("stencil", ctypes.c_int), ("eta_over_s", ctypes.c_double),
+                ("T_R_GeV", ctypes.c_double), ("n_unit_fm3", ctypes.c_double), ("dx_fm", ctypes.c_double)]
 
 
 _lib = None
@@ -99,6 +106,17 @@ def lib():
     L.rlbm_mlp_get_params.argtypes = [vp, fp, fp]
     L.rlbm_set_landau_guess.argtypes = [vp, vp]
     L.rlbm_landau_guess_fields.argtypes = [vp, vp, vp]
+    L.rlbm_batch_create.argtypes = [ctypes.POINTER(vp), ci, ctypes.POINTER(vp), ci, ctypes.POINTER(Problem), cd, ci]
+    L.rlbm_batch_destroy.argtypes = [vp]
+    L.rlbm_batch_population_bytes.argtypes = [vp]
+    L.rlbm_batch_population_bytes.restype = ctypes.c_size_t
+    L.rlbm_batch_sites.argtypes = [vp]
+    L.rlbm_batch_sites.restype = ctypes.c_longlong
+    L.rlbm_batch_init.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.rlbm_batch_step_persistent.argtypes = [vp, ci, ci, vp, vp]
+    L.rlbm_batch_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.rlbm_batch_get_health.argtypes = [vp, ctypes.POINTER(ctypes.c_uint), ctypes.POINTER(ctypes.c_ulonglong),
+                                        ctypes.POINTER(ctypes.c_uint), vp]
     L.rlbm_last_error.argtypes = [vp]
     L.rlbm_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -331,3 +349,72 @@ class Solver:
         dt = {"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.float16}[self.precision]
         buf = self.pop[0] if (self.step_count() % 2 == 0) else self.pop[1]
         return buf.view(dt).view(self.info["q"], -1)
+
+
+class Batch:
+    """Batched 1D problems advanced in one persistent launch.  stencils: list of
+    Solver objects built with dim=1, precision='fp32'; problems: list of dicts
+    with nx, stencil (index), eta_over_s, T_R_GeV, n_unit_fm3, dx_fm."""
+
+    def __init__(self, stencils, problems, landau_tol=0.0, landau_maxit=0):
+        import torch
+        self.torch = torch
+        self._stencils = stencils
+        arr = (ctypes.c_void_p * len(stencils))(*[s.ctx.value for s in stencils])
+        pr = (Problem * len(problems))(*[Problem(p["nx"], p["stencil"], p["eta_over_s"], p["T_R_GeV"],
+                                                 p["n_unit_fm3"], p["dx_fm"]) for p in problems])
+        h = ctypes.c_void_p()
+        _check(lib().rlbm_batch_create(ctypes.byref(h), len(stencils), arr, len(problems), pr, float(landau_tol),
+                                       int(landau_maxit)))
+        self.h = h
+        self.sites = lib().rlbm_batch_sites(h)
+        self.problems = problems
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().rlbm_batch_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream().cuda_stream)
+
+    def init(self, n, T, ux):
+        torch = self.torch
+        nbytes = lib().rlbm_batch_population_bytes(self.h)
+        self.pop = [torch.empty(nbytes, dtype=torch.uint8, device=n.device) for _ in range(2)]
+        self._fields = (n, T, ux)
+        _check(lib().rlbm_batch_init(self.h, n.data_ptr(), T.data_ptr(), ux.data_ptr(), self.pop[0].data_ptr(),
+                                     self.pop[1].data_ptr(), nbytes, self._stream()))
+
+    def step(self, nsteps, sample_every=0):
+        """Advances nsteps in one launch; returns the samples tensor
+        [ceil(nsteps / sample_every), sites, 12] when sample_every > 0."""
+        torch = self.torch
+        samples = None
+        if sample_every > 0:
+            ns = (nsteps + sample_every - 1) // sample_every
+            samples = torch.empty((ns, self.sites, 12), dtype=torch.float32, device=self.pop[0].device)
+        _check(lib().rlbm_batch_step_persistent(self.h, int(nsteps), int(sample_every),
+                                                samples.data_ptr() if samples is not None else None,
+                                                self._stream()))
+        return samples
+
+    def moments(self):
+        torch = self.torch
+        out = {k: torch.empty(self.sites, dtype=torch.float64, device=self.pop[0].device)
+               for k in ("n", "eps", "T", "P", "ux")}
+        _check(lib().rlbm_batch_moments(self.h, out["n"].data_ptr(), out["eps"].data_ptr(), out["T"].data_ptr(),
+                                        out["P"].data_ptr(), out["ux"].data_ptr(), self._stream()))
+        return out
+
+    def health(self):
+        f = ctypes.c_uint()
+        s = ctypes.c_ulonglong()
+        m = ctypes.c_uint()
+        rc = lib().rlbm_batch_get_health(self.h, ctypes.byref(f), ctypes.byref(s), ctypes.byref(m), self._stream())
+        if rc not in (RLBM_OK, RLBM_ENUMERIC):
+            _check(rc)
+        return {"flags": f.value, "iter_sum": s.value, "iter_max": m.value, "fatal": rc == RLBM_ENUMERIC}

@@ -99,3 +99,36 @@ def random_smooth(nx, ny, seed=0, umax=0.3):
     T = 1.0 + field(0.1)
     ux, uy = field(umax / 3), field(umax / 3)
     return n, T, ux, uy
+
+
+# stencils available for the batched workload, by mbar
+BATCH_ZETAS = {0.36: "zeta036", 1.0: "zeta1", 5.0: "zeta5", 10.0: "zeta10"}
+
+
+def batched_riemann(nprob=64, seed=0, lmin=256, lmax=4096, zeta_range=(0.1, 10.0), eta_s_range=(0.05, 0.5),
+                    ratio_range=(2.0, 50.0), dx_fm=0.002):
+    """Independent quasi-1D shock tubes: length L ~ U{lmin..lmax}, mbar drawn
+    log-uniform in zeta_range and snapped (in log) to the nearest available
+    stencil, eta/s uniform, pressure ratio r log-uniform.  Left state
+    T = 0.35 GeV, P = 5.43 GeV/fm^3; right state T r^(-1/4), n r^(-3/4) (P ~ T^4);
+    T_R the geometric mean of the two temperatures; dx = 0.002 fm (the
+    paper's lattice spacing); u = 0; interface at L/2.
+    Returns (problems, fields) with fields = (n, T, ux) concatenated."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    zs = np.array(sorted(BATCH_ZETAS))
+    probs, ns, Ts, us = [], [], [], []
+    for _ in range(nprob):
+        L = int(rng.integers(lmin, lmax + 1))
+        zeta_drawn = float(np.exp(rng.uniform(np.log(zeta_range[0]), np.log(zeta_range[1]))))
+        zeta = float(zs[np.argmin(np.abs(np.log(zs) - np.log(zeta_drawn)))])
+        eta_s = float(rng.uniform(*eta_s_range))
+        r = float(np.exp(rng.uniform(np.log(ratio_range[0]), np.log(ratio_range[1]))))
+        TL, TRt = 0.35, 0.35 * r ** -0.25
+        TR = (TL * TRt) ** 0.5
+        left = np.arange(L) < L // 2
+        ns.append(np.where(left, 1.0, r ** -0.75))
+        Ts.append(np.where(left, TL / TR, TRt / TR))
+        us.append(np.zeros(L))
+        probs.append({"nx": L, "stencil_name": BATCH_ZETAS[zeta], "zeta_drawn": zeta_drawn, "zeta": zeta,
+                      "eta_over_s": eta_s, "ratio": r, "T_R_GeV": TR, "n_unit_fm3": 5.43 / 0.35, "dx_fm": dx_fm})
+    return probs, (np.concatenate(ns), np.concatenate(Ts), np.concatenate(us))
