@@ -100,7 +100,7 @@ typedef struct {
 typedef struct {
   int q3;                /* populations of the 3D stencil */
   int q;                 /* populations after exact in-plane merging (the
-                            number of planes the GPU stores) */
+                            number of classes the GPU stores per site) */
   double v0;             /* v0 in use */
   double v0_lo, v0_hi;   /* positive-weight window found (search only) */
   double weights[16];    /* weight per group (per population of the group) */
@@ -144,7 +144,8 @@ int rlbm_eos_temperature_host(double zeta, const double* e, int n, double* T);
 int rlbm_destroy(rlbm_ctx* ctx);
 
 /* Bytes of one population buffer for an nx x ny lattice in this context's
- * precision (planes padded to 256 bytes).  0 on invalid sizes. */
+ * precision: storage rows (lattice rows plus ghost rows) of q class rows each
+ * (ghost columns included), padded to 128 elements.  0 on invalid sizes. */
 size_t rlbm_population_bytes(const rlbm_ctx* ctx, int nx, int ny);
 
 typedef struct {
@@ -210,7 +211,7 @@ int rlbm_get_health(rlbm_ctx* ctx, unsigned* flags, unsigned long long* landau_i
 /* Completed time steps since rlbm_init_fields. */
 long long rlbm_step_count(const rlbm_ctx* ctx);
 
-/* Copies the current state (population planes in storage precision, as laid
+/* Copies the current state (population buffer in storage precision, as laid
  * out by the library) to dst (device or host, pop_bytes) and back; with the
  * step count this is the whole state (checkpoint / resume). */
 int rlbm_save_state(rlbm_ctx* ctx, void* dst, size_t bytes, long long* step, int* layout_flag, void* stream);

@@ -96,26 +96,42 @@ __device__ __forceinline__ double eos_temperature(double e, double zeta, unsigne
 // Inverse EOS from the per-stencil table: T = u g(u), u = e - zeta, with g a
 // Chebyshev series on the quarter-octave of u (built on the host in long
 // double from the same equation); Newton fallback outside the tabulated range.
+// The lanes of a wave are served one distinct piece at a time (the piece index
+// is made uniform, so its coefficients come through scalar loads): smooth
+// fields put a wave's sites in one or two pieces, and no vector memory access
+// is needed.
 __device__ __forceinline__ double eos_temperature_tab(TabPtr tb, double e, double zeta,
                                                      unsigned& flags) {
   const double u = e - zeta;
   int ex;
   const double m = frexp(u, &ex);          // u = m 2^ex, m in [1/2, 1)
   const int o = ex - 1 - RLBM_EOS_KMIN;
-  if (!(u > 0.0) || o < 0 || o >= RLBM_EOS_NOCT) return eos_temperature(e, zeta, flags);
+  const bool intab = u > 0.0 && o >= 0 && o < RLBM_EOS_NOCT;
   const double m2 = 2.0 * m;                // [1, 2)
   const int piece = min((int)((m2 - 1.0) * 4.0), 3);
   const double t = (m2 - 1.0 - 0.25 * piece) * 8.0 - 1.0;
-  const __attribute__((address_space(4))) double* c = tb->eos[o * 4 + piece];
+  const int idx = intab ? o * 4 + piece : -1;
   const double t2 = 2.0 * t;
-  double b1 = 0.0, b2 = 0.0;
+  double g = 0.0;
+  bool todo = intab;
+  for (unsigned long long pend = __builtin_amdgcn_ballot_w64(todo); pend != 0ull;
+       pend = __builtin_amdgcn_ballot_w64(todo)) {
+    const int iu = __builtin_amdgcn_readlane(idx, (int)__builtin_ctzll(pend));
+    const __attribute__((address_space(4))) double* c = tb->eos[iu];
+    double b1 = 0.0, b2 = 0.0;
 #pragma unroll
-  for (int j = RLBM_EOS_DEG - 1; j >= 1; --j) {
-    const double b0 = fma(t2, b1, c[j] - b2);
-    b2 = b1;
-    b1 = b0;
+    for (int j = RLBM_EOS_DEG - 1; j >= 1; --j) {
+      const double b0 = fma(t2, b1, c[j] - b2);
+      b2 = b1;
+      b1 = b0;
+    }
+    if (todo && idx == iu) {
+      g = fma(t, b1, c[0] - b2);
+      todo = false;
+    }
   }
-  return u * fma(t, b1, c[0] - b2);
+  if (!intab) return eos_temperature(e, zeta, flags);
+  return u * g;
 }
 
 // Landau frame by Newton's method on the characteristic polynomial of the

@@ -1,8 +1,9 @@
 // HIP kernels (gfx950) and C ABI of the relativistic lattice Boltzmann library
 // (arXiv:1703.04605, second-order model of Sec. III).
 //
-// Data layout in HBM: one plane per population class j, planes[j][y][x],
-// x fastest, planes padded to 128 elements; two buffers (ping-pong).
+// Data layout in HBM: row-interleaved classes, f[y][j][x] with x fastest
+// (the Q class rows of one lattice row are consecutive), padded to 128
+// elements; two buffers (ping-pong).
 // A time step is one fused kernel: each thread owns one site, pulls the Q
 // class values f_j(x - n_j) from the previous post-collision state (exact
 // streaming, Sec. III.B), keeps them in registers, reduces the nine in-plane
@@ -14,6 +15,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -26,6 +28,13 @@
 namespace rlbm {
 
 constexpr int kBlock = 256;
+constexpr int kWave = 64;
+// fourth word of a raw buffer descriptor on CDNA: 32-bit data format, no
+// swizzle, untyped loads and stores address bytes
+constexpr int kRsrcWord3 = 0x00020000;
+constexpr int kRecAll = 0x7FFFFFFF;        // records of a step descriptor
+constexpr int kRecOut = (int)0x80000000u;  // a lane offset beyond them
+typedef unsigned U32x2 __attribute__((ext_vector_type(2)));
 constexpr long long kPlaneAlign = 128;  // elements
 constexpr double kHbarC = 0.1973269804; // GeV fm
 
@@ -46,35 +55,25 @@ __device__ __forceinline__ typename Traits<P>::S to_store(typename Traits<P>::A 
   else return v;
 }
 
-// Reduces health flags and Landau iteration counts over the block into the
-// block's own slot (one slot per logical block: no atomics, no races).
-__device__ __forceinline__ void block_stats(RlbmSlot* slots, int lb, unsigned flags, unsigned iters) {
-  __shared__ unsigned s_f[kBlock / 64], s_m[kBlock / 64], s_s[kBlock / 64];
-  unsigned fl = flags, mx = iters, sm = iters;
+// Reduces health flags and Landau iteration counts over the wave into the
+// wave's own slot (one slot per wave of the persistent grid: no atomics, no
+// races).
+__device__ __forceinline__ void wave_stats(RlbmSlot* slots, int gw, unsigned flags, unsigned iters_max,
+                                           unsigned iters_sum) {
+  unsigned fl = flags, mx = iters_max;
+  unsigned long long sm = iters_sum;
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     fl |= __shfl_xor(fl, off);
     mx = max(mx, (unsigned)__shfl_xor(mx, off));
     sm += __shfl_xor(sm, off);
   }
-  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    s_f[w] = fl;
-    s_m[w] = mx;
-    s_s[w] = sm;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int i = 1; i < kBlock / 64; ++i) {
-      fl |= s_f[i];
-      mx = max(mx, s_m[i]);
-      sm += s_s[i];
-    }
-    RlbmSlot s = slots[lb];
+    RlbmSlot s = slots[gw];
     s.flags |= fl;
     s.iter_max = max(s.iter_max, mx);
     s.iter_sum += sm;
-    slots[lb] = s;
+    slots[gw] = s;
   }
 }
 
@@ -134,15 +133,15 @@ __device__ __forceinline__ unsigned ghost_mask(int x, int n, int S, int bc) {
 
 __device__ __forceinline__ int ghost_coord(int i, int n, int S) { return i < S ? i - S : n + (i - S); }
 
-// Writes v to every ghost copy of site (x, y) in plane q (the owner copy is
+// Writes v to every ghost copy of site (x, y) in class q (the owner copy is
 // written by the caller).
 template <typename S>
 __device__ __forceinline__ void store_ghosts(S* __restrict__ q, const RlbmLayout& L, int x, int y, unsigned xm,
                                              unsigned ym, S v) {
   for (unsigned m = xm; m; m &= m - 1)
-    q[(long long)(y + L.GY) * L.W + ghost_coord(__builtin_ctz(m), L.nx, L.Sx) + L.GX] = v;
+    q[(long long)(y + L.GY) * L.rs + ghost_coord(__builtin_ctz(m), L.nx, L.Sx) + L.GX] = v;
   for (unsigned r = ym; r; r &= r - 1) {
-    const long long row = (long long)(ghost_coord(__builtin_ctz(r), L.ny, L.Sy) + L.GY) * L.W;
+    const long long row = (long long)(ghost_coord(__builtin_ctz(r), L.ny, L.Sy) + L.GY) * L.rs;
     q[row + x + L.GX] = v;
     for (unsigned m = xm; m; m &= m - 1) q[row + ghost_coord(__builtin_ctz(m), L.nx, L.Sx) + L.GX] = v;
   }
@@ -180,8 +179,14 @@ __device__ __forceinline__ float silu_f(float z) { return z * __builtin_amdgcn_r
 __device__ __forceinline__ void mlp_wave(const RlbmStepArgs& a, const float xin[9], float out[3]) {
   const int l = threadIdx.x & 63;
   const int half = l >> 5;
-  const v4s* __restrict__ frag = (const v4s*)a.mlp_frag;
-  const v16f* __restrict__ bias = (const v16f*)a.mlp_bias;
+  // The weight pointers pass through an empty asm statement so that the
+  // fragment loads stay at their use in every tile of the persistent loop
+  // instead of being hoisted out of it (which would keep all fragments live).
+  const unsigned short* fp = a.mlp_frag;
+  const float* bp = a.mlp_bias;
+  asm volatile("" : "+s"(fp), "+s"(bp));
+  const v4s* __restrict__ frag = (const v4s*)fp;
+  const v16f* __restrict__ bias = (const v16f*)bp;
 
   // layer-1 B operands: inputs 8s + 4 half + i of site (l % 32) + 32 t
   v4s bop[2][8];
@@ -275,69 +280,129 @@ __device__ __forceinline__ void mlp_destandardise(const RlbmStepArgs& a, double 
 // wave's arithmetic with other waves' loads, while the class values of the
 // largest stencils still fit in registers.
 constexpr int step_waves(int qn, int p, bool g) {
-  return g ? (p == RLBM_FP64 ? (qn <= 24 ? 2 : 1) : (qn <= 24 ? 3 : 2))
-           : p == RLBM_FP64 ? (qn <= 48 ? 3 : qn <= 80 ? 2 : 1) : (qn <= 48 ? 4 : qn <= 80 ? 3 : 2);
+  return g ? (p == RLBM_FP64 ? 1 : (qn <= 24 ? 3 : 2))
+           : p == RLBM_FP64 ? (qn <= 48 ? 3 : 2) : (qn <= 48 ? 4 : 3);
 }
 
-// One time step for a block of kBlock consecutive sites of one row, for a
-// stencil of at most QN classes.  The class loops are fully unrolled, so the
-// populations stay in registers; the pull loop is unguarded so all pulls are
-// issued back to back (classes Q <= j < QN read class 0's source and have
-// all-zero table rows), the arithmetic loops skip them.
-template <int QN, int P, bool G>
+// s_waitcnt operand that waits for LDS / scalar memory only (the vector
+// memory and export counters at their maxima).
+constexpr int kWaitLgkm0 = 0xC07F;
+
+// Per-class table rows as whole structs, so each is fetched by wide scalar
+// loads (moments: the nine monomials; equilibrium: M_j, n_j).
+template <int P> struct Rows;
+template <> struct Rows<RLBM_FP64> {
+  struct alignas(16) M { double v[RLBM_ROWMD]; };
+  struct alignas(16) E { double v[RLBM_ROWD]; };
+  static __device__ __forceinline__ const __attribute__((address_space(4))) M* m(TabPtr t) {
+    return (const __attribute__((address_space(4))) M*)t->rowmd;
+  }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) E* e(TabPtr t) {
+    return (const __attribute__((address_space(4))) E*)t->rowd;
+  }
+};
+template <> struct Rows<RLBM_FP32_DEV> {
+  struct alignas(16) M { float v[RLBM_ROWMF]; };
+  struct alignas(16) E { float v[RLBM_ROWF]; };
+  static __device__ __forceinline__ const __attribute__((address_space(4))) M* m(TabPtr t) {
+    return (const __attribute__((address_space(4))) M*)t->rowmf;
+  }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) E* e(TabPtr t) {
+    return (const __attribute__((address_space(4))) E*)t->rowf;
+  }
+};
+template <> struct Rows<RLBM_FP16_DEV> : Rows<RLBM_FP32_DEV> {};
+
+template <typename R>
+__device__ __forceinline__ R load_row(const __attribute__((address_space(4))) R* p) {
+  R r;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(r.v) / sizeof(r.v[0])); ++i) r.v[i] = p->v[i];
+  return r;
+}
+
+// One time step for one tile per wave (kWave consecutive sites of a row), for
+// a stencil of QMIN..QN classes.  The class loops are fully unrolled, so the
+// populations stay in registers.
+//
+// Addressing: one buffer descriptor per tile and buffer, based at the lowest
+// address any pull of the tile can reach, with 2^31 - 1 records; every class
+// access adds a precomputed per-class scalar offset (from the offset table,
+// below 2^31) to the shared lane offset.  Lanes past the row end re-read the
+// row's last site, and their stores use the lane offset 2^31, beyond the
+// records, which the hardware drops.  Classes Q <= j < QN (padding up to the
+// kernel's class count; only j >= QMIN can be padding) read class 0's source,
+// have all-zero table rows, and store through a descriptor with no records.
+//
+// Table rows: row j + 1 is requested right after the wait for row j, before
+// class j is processed (scalar loads complete in any order, so every wait is
+// for all of them).  In the FP16 mode the rows carry the per-class scale, so
+// the kernel relaxes the stored ratios h_j = (f_j - f^ref_j) / f^ref_j directly.
+template <int QN, int QMIN, int P, bool G>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves(QN, P, G))))
 k_step(RlbmStepArgs a) {
   using S = typename Traits<P>::S;
   using A = typename Traits<P>::A;
-  typedef const __attribute__((address_space(4))) int* OffPtr;
+  typedef const __attribute__((address_space(4))) unsigned* OffPtr;
   const TabPtr tb = as_tab(a.tab);
   const RlbmLayout& L = a.L;
+  const int lane = (int)threadIdx.x & (kWave - 1);
+  const int t = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (kBlock / kWave) +
+                __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  if (t >= a.ntiles) return;  // whole wave
   const int Q = tb->c.Q;
-  const int lb = xcd_remap(blockIdx.x, gridDim.x);
-  const int y = lb / a.blocks_x;
-  const int x0 = (lb - y * a.blocks_x) * kBlock;
-  const int x = x0 + (int)threadIdx.x;
+  const int y = t / a.tiles_x;
+  const int x0 = (t - y * a.tiles_x) * kWave;
+  const int x = x0 + lane;
   const bool active = x < L.nx;
-  const unsigned lo = (unsigned)((active ? x : L.nx - 1) - x0);   // lane offset from the block base
-  const long long base = (long long)(y + L.GY) * L.W + L.GX + x0;  // uniform
-  const S* __restrict__ src = (const S*)a.src + base;
-  S* __restrict__ dst = (S*)a.dst;
-
-  // source offsets of all classes, fetched together before any pull
-  const OffPtr offp = (OffPtr)a.offs;
-  int off[QN];
-#pragma unroll
-  for (int j = 0; j < QN; ++j) off[j] = offp[j];
+  const int nvalid = min(kWave, L.nx - x0);
+  const long long lo = (long long)(y + L.GY - L.Sy) * L.rs + L.GX - L.Sx + x0;
+  const __amdgpu_buffer_rsrc_t rs_ld = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)((const char*)a.src + lo * (long long)sizeof(S)), (short)0, kRecAll, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rs_st = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)((char*)a.dst + lo * (long long)sizeof(S)), (short)0, kRecAll, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rs_none = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)((char*)a.dst + lo * (long long)sizeof(S)), (short)0, 0, kRsrcWord3);
+  const int vld = min(lane, nvalid - 1) * (int)sizeof(S);
+  const int vst = active ? lane * (int)sizeof(S) : kRecOut;
+  const OffPtr pull = (OffPtr)a.offs;
+  const OffPtr own = (OffPtr)a.offs_st;
 
   // pull: f_j(x, t) = f*_j(x - n_j, t - 1) (exact streaming)
-  A f[QN];
+  S raw[QN];
 #pragma unroll
   for (int j = 0; j < QN; ++j) {
-    const S v = (src + off[j])[lo];
-    if constexpr (P == RLBM_FP16_DEV) f[j] = (float)v * tb->rowf[j][RLBM_R_SCALE];
-    else f[j] = v;
+    if constexpr (P == RLBM_FP64)
+      raw[j] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs_ld, vld, pull[j], 0));
+    else if constexpr (P == RLBM_FP32_DEV)
+      raw[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs_ld, vld, pull[j], 0));
+    else
+      raw[j] = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs_ld, vld, pull[j], 0));
   }
 
-  // moments (eq. mj-discrete-second-moment); deviation modes add the exact
-  // float64 moments of the reference state
+  // moments (eq. mj-discrete-second-moment) as one multiply-add per
+  // monomial; deviation modes add the exact float64 moments of the reference
+  A f[QN];
   A m[9] = {A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0)};
-  // (the uniform guards of the arithmetic loops also keep the compiler from
-  // hoisting every class's table reads, which would spill registers)
+  {
+    const auto* rows = Rows<P>::m(tb);
+    typename Rows<P>::M cur = load_row(rows);
 #pragma unroll
-  for (int j = 0; j < QN; ++j) {
-    if (j < Q) {
-      A p0, px, py;
-      if constexpr (P == RLBM_FP64) {
-        p0 = tb->rowd[j][RLBM_R_P0]; px = tb->rowd[j][RLBM_R_PX]; py = tb->rowd[j][RLBM_R_PY];
-      } else {
-        p0 = tb->rowf[j][RLBM_R_P0]; px = tb->rowf[j][RLBM_R_PX]; py = tb->rowf[j][RLBM_R_PY];
-      }
-      const A a0 = f[j] * p0, ax = f[j] * px, ay = f[j] * py;
-      m[0] += a0; m[1] += ax; m[2] += ay;
-      m[3] = fma(a0, p0, m[3]); m[4] = fma(a0, px, m[4]); m[5] = fma(a0, py, m[5]);
-      m[6] = fma(ax, px, m[6]); m[7] = fma(ax, py, m[7]); m[8] = fma(ay, py, m[8]);
+    for (int j = 0; j < QN; ++j) {
+      __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+      const typename Rows<P>::M nxt = load_row(rows + (j + 1 < QN ? j + 1 : j));
+      __builtin_amdgcn_sched_barrier(0);
+      f[j] = (A)raw[j];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) m[k] = fma(f[j], (A)cur.v[k], m[k]);
+      __builtin_amdgcn_sched_barrier(0);
+      cur = nxt;
     }
   }
+  // all nine sums are formed here, next to the class values (not sunk past
+  // the Landau solve, which would re-fetch the rows)
+#pragma unroll
+  for (int k = 0; k < 9; ++k) asm volatile("" : "+v"(m[k]));
   double md[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) md[k] = (P == RLBM_FP64) ? (double)m[k] : tb->c.ref_mom[k] + (double)m[k];
@@ -363,42 +428,45 @@ k_step(RlbmStepArgs a) {
   const A W0 = (A)w0, WX = (A)wx, WY = (A)wy;
 
   // equilibrium (eq. mj-discrete-feq) and relaxation, stored at the own site
+  {
+    const auto* rows = Rows<P>::e(tb);
+    typename Rows<P>::E cur = load_row(rows);
 #pragma unroll
-  for (int j = 0; j < QN; ++j) {
-    if (j < Q) {
-      A feq, dx, dy;
-      if constexpr (P == RLBM_FP64) {
-        const auto* r = tb->rowd[j];
-        feq = nb[0] * r[0];
+    for (int j = 0; j < QN; ++j) {
+      __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+      const typename Rows<P>::E nxt = load_row(rows + (j + 1 < QN ? j + 1 : j));
+      __builtin_amdgcn_sched_barrier(0);
+      A feq = nb[0] * (A)cur.v[0];
 #pragma unroll
-        for (int k = 1; k < RLBM_NB; ++k) feq = fma(nb[k], r[k], feq);
-        dx = r[RLBM_R_NX]; dy = r[RLBM_R_NY];
-      } else {
-        const auto* r = tb->rowf[j];
-        feq = nb[0] * r[0];
-#pragma unroll
-        for (int k = 1; k < RLBM_NB; ++k) feq = fma(nb[k], r[k], feq);
-        dx = r[RLBM_R_NX]; dy = r[RLBM_R_NY];
-      }
-      const A om = fma(WY, dy, fma(WX, dx, W0));
+      for (int k = 1; k < RLBM_NB; ++k) feq = fma(nb[k], (A)cur.v[k], feq);
+      const A om = fma(WY, (A)cur.v[RLBM_R_NY], fma(WX, (A)cur.v[RLBM_R_NX], W0));
       f[j] = fma(-om, f[j] - feq, f[j]);
-      S out;
-      if constexpr (P == RLBM_FP16_DEV) out = (_Float16)(f[j] * tb->rowf[j][RLBM_R_INVSCALE]);
-      else out = f[j];
-      if (active) (dst + ((long long)j * L.plane + base))[lo] = out;
+      const __amdgpu_buffer_rsrc_t r = (j < QMIN || j < Q) ? rs_st : rs_none;
+      if constexpr (P == RLBM_FP64)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, f[j]), r, vst, own[j], 0);
+      else if constexpr (P == RLBM_FP32_DEV)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, f[j]), r, vst, own[j], 0);
+      else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)f[j]), r, vst, own[j], 0);
+      __builtin_amdgcn_sched_barrier(0);
+      cur = nxt;
     }
   }
 
   // ghost copies are needed only near the lattice edges (uniform test)
   const unsigned ym = ghost_mask(y, L.ny, L.Sy, L.bc_y);
-  const bool xedge = x0 < L.Sx || x0 + kBlock > L.nx - L.Sx;
-  if ((xedge || ym != 0u) && active) {
+  const bool xedge = x0 < L.Sx || x0 + kWave > L.nx - L.Sx;
+  if (xedge || ym != 0u) {
+    S* __restrict__ dst = (S*)a.dst;
     const unsigned xm = xedge ? ghost_mask(x, L.nx, L.Sx, L.bc_x) : 0u;
+    if (active) {
 #pragma unroll
-    for (int j = 0; j < QN; ++j)
-      if (j < Q) store_ghosts(dst + (long long)j * L.plane, L, x, y, xm, ym, to_store<P>(f[j], tb, j));
+      for (int j = 0; j < QN; ++j)
+        if (j < Q) store_ghosts(dst + (long long)j * L.cs, L, x, y, xm, ym, (S)f[j]);
+    }
   }
-  block_stats(a.slots, lb, active ? mac.flags : 0u, active ? (unsigned)mac.iters : 0u);
+  wave_stats(a.slots, t, active ? mac.flags : 0u, active ? (unsigned)mac.iters : 0u,
+             active ? (unsigned)mac.iters : 0u);
 }
 
 // ------------------------------------------------------------------ moments
@@ -416,7 +484,7 @@ __global__ void __launch_bounds__(kBlock) k_moments(RlbmMomArgs a) {
   for (int j = 0; j < tb->c.Q; ++j) {
     const int sx = a.shift ? x - tb->nx[j] : x, sy = a.shift ? y - tb->ny[j] : y;
     const double f =
-        (double)to_arith<P>(src[(long long)j * L.plane + (long long)(sy + L.GY) * L.W + sx + L.GX], tb, j);
+        (double)to_arith<P>(src[(long long)j * L.cs + (long long)(sy + L.GY) * L.rs + sx + L.GX], tb, j);
     const double p0 = tb->p0[j], px = tb->px[j], py = tb->py[j];
     m[0] += f * p0; m[1] += f * px; m[2] += f * py;
     m[3] += f * p0 * p0; m[4] += f * p0 * px; m[5] += f * p0 * py;
@@ -455,11 +523,11 @@ __global__ void __launch_bounds__(kBlock) k_init(RlbmInitArgs a) {
   double nb[RLBM_NB];
   for (int k = 0; k < RLBM_NB; ++k) nb[k] = n * b[k] - (P == RLBM_FP64 ? 0.0 : tb->c.nb_ref[k]);
   S* __restrict__ dst = (S*)a.dst;
-  const long long o = (long long)(y + L.GY) * L.W + x + L.GX;
+  const long long o = (long long)(y + L.GY) * L.rs + x + L.GX;
   for (int j = 0; j < tb->c.Q; ++j) {
     double fe = 0.0;
     for (int k = 0; k < RLBM_NB; ++k) fe = fma(nb[k], tb->M[k][j], fe);
-    dst[(long long)j * L.plane + o] = to_store<P>((typename Traits<P>::A)fe, tb, j);
+    dst[(long long)j * L.cs + o] = to_store<P>((typename Traits<P>::A)fe, tb, j);
   }
 }
 
@@ -469,17 +537,18 @@ using StepFn = void (*)(RlbmStepArgs);
 
 // Class-count buckets: exact fits for the configured stencils (19: zeta = 1
 // in 1D, 39: G1..G6 in 2D, 44: zeta = 1 in 2D, 73: the 133-population stencil
-// in 2D) and padded buckets for any other stencil.
+// in 2D) and padded buckets for any other stencil; the second argument is the
+// bucket's smallest class count.
 template <int P, bool G>
 StepFn step_kernel(int Q) {
-  if (Q <= 19) return k_step<19, P, G>;
-  if (Q <= 24) return k_step<24, P, G>;
-  if (Q <= 39) return k_step<39, P, G>;
-  if (Q <= 44) return k_step<44, P, G>;
-  if (Q <= 48) return k_step<48, P, G>;
-  if (Q <= 73) return k_step<73, P, G>;
-  if (Q <= 80) return k_step<80, P, G>;
-  return k_step<160, P, G>;
+  if (Q <= 19) return k_step<19, 1, P, G>;
+  if (Q <= 24) return k_step<24, 20, P, G>;
+  if (Q <= 39) return k_step<39, 25, P, G>;
+  if (Q <= 44) return k_step<44, 40, P, G>;
+  if (Q <= 48) return k_step<48, 45, P, G>;
+  if (Q <= 73) return k_step<73, 49, P, G>;
+  if (Q <= 80) return k_step<80, 74, P, G>;
+  return k_step<160, 81, P, G>;
 }
 
 // The learned-guess kernels are built for float32 storage, the path the
@@ -505,7 +574,7 @@ __global__ void __launch_bounds__(kBlock) k_guess(RlbmStepArgs a, float* __restr
   double md[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int j = 0; j < tb->c.Q; ++j) {
     const int sx = a.shift ? x - tb->nx[j] : x, sy = a.shift ? y - tb->ny[j] : y;
-    const long long idx = (long long)j * L.plane + (long long)(sy + L.GY) * L.W + sx + L.GX;
+    const long long idx = (long long)j * L.cs + (long long)(sy + L.GY) * L.rs + sx + L.GX;
     double f;
     if (tb->c.precision == RLBM_FP64) f = ((const double*)a.src)[idx];
     else if (tb->c.precision == RLBM_FP32_DEV) f = ((const float*)a.src)[idx];
@@ -549,8 +618,9 @@ struct rlbm_ctx {
   int shifted = 0;
   long long steps = 0;
   RlbmSlot* d_slots = nullptr;
-  int* d_offs = nullptr;  // [0, QMAX): local read offsets, [QMAX, 2 QMAX): pull offsets
-  int nblocks = 0, blocks_x = 0;
+  unsigned* d_offs = nullptr;  // [0, QMAX): in-place byte offsets, [QMAX, 2 QMAX): pull byte offsets
+  int tiles_x = 0, ntiles = 0;  // wave tiles (kWave sites of a row)
+  int nslots = 0;               // health slots: one per tile
   double tk1 = 0, tk2 = 0;
   const rlbm_mlp* guess = nullptr;
   char err[512] = {0};
@@ -610,8 +680,9 @@ extern "C" int rlbm_destroy(rlbm_ctx* c) {
   return RLBM_OK;
 }
 
-// Plane layout: ghost columns padded to 32 elements so every interior row
-// starts on a 32-element boundary; ghost rows of the max |n_y|.
+// Row-interleaved layout: ghost columns padded to 32 elements so every
+// interior class row starts on a 32-element boundary; ghost rows of the max
+// |n_y|; the Q class rows of a lattice row are consecutive.
 static RlbmLayout make_layout(const RlbmConsts& k, int nx, int ny, int bc_x, int bc_y) {
   RlbmLayout L;
   L.nx = nx;
@@ -621,8 +692,10 @@ static RlbmLayout make_layout(const RlbmConsts& k, int nx, int ny, int bc_x, int
   L.GX = (L.Sx + 31) / 32 * 32;
   L.GY = L.Sy;
   L.W = (L.GX + nx + L.Sx + 31) / 32 * 32;
-  long long s = (long long)(ny + 2 * L.GY) * L.W;
-  L.plane = (s + kPlaneAlign - 1) / kPlaneAlign * kPlaneAlign;
+  L.cs = L.W;
+  L.rs = (long long)k.Q * L.W;
+  const long long s = (long long)(ny + 2 * L.GY) * L.rs;
+  L.total = (s + kPlaneAlign - 1) / kPlaneAlign * kPlaneAlign;
   L.bc_x = bc_x;
   L.bc_y = bc_y;
   return L;
@@ -631,7 +704,7 @@ static RlbmLayout make_layout(const RlbmConsts& k, int nx, int ny, int bc_x, int
 extern "C" size_t rlbm_population_bytes(const rlbm_ctx* c, int nx, int ny) {
   if (!c || nx <= 0 || ny <= 0) return 0;
   RlbmLayout L = make_layout(c->h_tab->c, nx, ny, 0, 0);
-  return (size_t)c->h_tab->c.Q * (size_t)L.plane * elem_size(c->h_tab->c.precision);
+  return (size_t)L.total * elem_size(c->h_tab->c.precision);
 }
 
 extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n, const double* T,
@@ -666,32 +739,38 @@ extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const
   c->buf[1] = popB;
   c->pop_bytes = pop_bytes;
   c->L = make_layout(k, lat->nx, lat->ny, lat->bc_x, lat->bc_y);
-  if ((long long)k.Q * c->L.plane >= (1LL << 31)) return fail(c, RLBM_EINVAL, "lattice too large for 32-bit offsets");
+  if (c->L.total >= (1LL << 31)) return fail(c, RLBM_EINVAL, "lattice too large (2^31 or more stored elements)");
   {
-    std::vector<int> offs(2 * RLBM_QMAX, 0);
-    for (int j = 0; j < k.Q; ++j) {
-      offs[j] = (int)(j * c->L.plane);
-      offs[RLBM_QMAX + j] = (int)(j * c->L.plane - (long long)c->h_tab->ny[j] * c->L.W - c->h_tab->nx[j]);
+    // byte offsets of each class's source from the lowest element a tile can
+    // reach (class 0 at (x0 - Sx, y - Sy)): [0, QMAX) in place (also the own
+    // storage the step writes), [QMAX, 2 QMAX) pulled
+    const long long es = k.precision == RLBM_FP64 ? 8 : k.precision == RLBM_FP32_DEV ? 4 : 2;
+    const long long base = (long long)c->L.Sy * c->L.rs + c->L.Sx;
+    std::vector<unsigned> offs(2 * RLBM_QMAX, 0);
+    for (int j = 0; j < RLBM_QMAX; ++j) {
+      const int jj = j < k.Q ? j : 0;  // padding classes read class 0's source
+      const long long own = base + jj * c->L.cs;
+      const long long src = own - (long long)c->h_tab->ny[jj] * c->L.rs - c->h_tab->nx[jj];
+      if (src < 0 || es * (own + c->L.Sy * c->L.rs + c->L.Sx + kWave) >= (1LL << 31))
+        return fail(c, RLBM_EINVAL, "class offsets out of range");
+      offs[j] = (unsigned)(es * own);
+      offs[RLBM_QMAX + j] = (unsigned)(es * src);
     }
-    for (int j = k.Q; j < RLBM_QMAX; ++j) {  // padding classes read class 0's source
-      offs[j] = offs[0];
-      offs[RLBM_QMAX + j] = offs[RLBM_QMAX];
-    }
-    if (!c->d_offs) HIPCHECK(c, hipMalloc((void**)&c->d_offs, sizeof(int) * 2 * RLBM_QMAX));
-    HIPCHECK(c, hipMemcpy(c->d_offs, offs.data(), sizeof(int) * 2 * RLBM_QMAX, hipMemcpyHostToDevice));
+    if (!c->d_offs) HIPCHECK(c, hipMalloc((void**)&c->d_offs, sizeof(unsigned) * 2 * RLBM_QMAX));
+    HIPCHECK(c, hipMemcpy(c->d_offs, offs.data(), sizeof(unsigned) * 2 * RLBM_QMAX, hipMemcpyHostToDevice));
   }
   c->cur = 0;
   c->shifted = 0;
   c->steps = 0;
-  c->blocks_x = (lat->nx + kBlock - 1) / kBlock;
-  int nb = c->blocks_x * lat->ny;
-  if (nb != c->nblocks) {
+  c->tiles_x = (lat->nx + kWave - 1) / kWave;
+  c->ntiles = c->tiles_x * lat->ny;
+  if (c->ntiles != c->nslots) {
     if (c->d_slots) HIPCHECK(c, hipFree(c->d_slots));
     c->d_slots = nullptr;
-    HIPCHECK(c, hipMalloc((void**)&c->d_slots, sizeof(RlbmSlot) * nb));
-    c->nblocks = nb;
+    HIPCHECK(c, hipMalloc((void**)&c->d_slots, sizeof(RlbmSlot) * c->ntiles));
+    c->nslots = c->ntiles;
   }
-  HIPCHECK(c, hipMemsetAsync(c->d_slots, 0, sizeof(RlbmSlot) * nb, s));
+  HIPCHECK(c, hipMemsetAsync(c->d_slots, 0, sizeof(RlbmSlot) * c->nslots, s));
   if (lat->tau_mode == RLBM_TAU_ETA_OVER_S) {
     const double TR = lat->T_R_GeV;
     c->tk1 = 1.5 * lat->eta_over_s * kHbarC * k.v0 / (lat->dx_fm * TR);
@@ -721,7 +800,8 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   RlbmStepArgs a;
   a.L = c->L;
-  a.blocks_x = c->blocks_x;
+  a.tiles_x = c->tiles_x;
+  a.ntiles = c->ntiles;
   a.tau_mode = c->lat.tau_mode;
   a.tau = c->lat.tau;
   a.tk1 = c->tk1;
@@ -739,12 +819,14 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
     for (int i = 0; i < 9; ++i) a.mlp_norm[9 + i] = 1.0f / c->guess->h_norm[9 + i];
   }
   StepFn fn = select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
+  const unsigned nwg = (unsigned)((c->ntiles + kBlock / kWave - 1) / (kBlock / kWave));
   for (int i = 0; i < nsteps; ++i) {
     a.src = c->buf[c->cur];
     a.dst = c->buf[1 - c->cur];
     a.shift = c->shifted;
     a.offs = c->d_offs + (c->shifted ? RLBM_QMAX : 0);
-    hipLaunchKernelGGL(fn, dim3(c->nblocks), dim3(kBlock), 0, s, a);
+    a.offs_st = c->d_offs;
+    hipLaunchKernelGGL(fn, dim3(nwg), dim3(kBlock), 0, s, a);
     HIPCHECK(c, hipGetLastError());
     c->cur ^= 1;
     c->shifted = 1;
@@ -784,8 +866,8 @@ extern "C" int rlbm_get_health(rlbm_ctx* c, unsigned* flags, unsigned long long*
   if (!c->have_fields) return fail(c, RLBM_ESTATE, "no fields");
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(c, hipStreamSynchronize(s));
-  std::vector<RlbmSlot> h(c->nblocks);
-  HIPCHECK(c, hipMemcpy(h.data(), c->d_slots, sizeof(RlbmSlot) * c->nblocks, hipMemcpyDeviceToHost));
+  std::vector<RlbmSlot> h(c->nslots);
+  HIPCHECK(c, hipMemcpy(h.data(), c->d_slots, sizeof(RlbmSlot) * c->nslots, hipMemcpyDeviceToHost));
   unsigned f = 0, mx = 0;
   unsigned long long sm = 0;
   for (auto& x : h) {
@@ -797,7 +879,7 @@ extern "C" int rlbm_get_health(rlbm_ctx* c, unsigned* flags, unsigned long long*
   if (iter_sum) *iter_sum = sm;
   if (iter_max) *iter_max = mx;
   if (reset) {
-    HIPCHECK(c, hipMemsetAsync(c->d_slots, 0, sizeof(RlbmSlot) * c->nblocks, s));
+    HIPCHECK(c, hipMemsetAsync(c->d_slots, 0, sizeof(RlbmSlot) * c->nslots, s));
     HIPCHECK(c, hipStreamSynchronize(s));
   }
   if (f & RLBM_H_FATAL) return fail(c, RLBM_ENUMERIC, "fatal health flag raised (0x%s)", "see flags");
@@ -905,11 +987,8 @@ __device__ __forceinline__ void batch_site(const RlbmBatchArgs& a, const RlbmBat
 #pragma unroll
   for (int j = 0; j < kBatchQ; ++j) {
     if (j < Q) {
-      const float p0 = tb->rowf[j][RLBM_R_P0], px = tb->rowf[j][RLBM_R_PX], py = tb->rowf[j][RLBM_R_PY];
-      const float a0 = f[j] * p0, ax = f[j] * px, ay = f[j] * py;
-      m[0] += a0; m[1] += ax; m[2] += ay;
-      m[3] = fmaf(a0, p0, m[3]); m[4] = fmaf(a0, px, m[4]); m[5] = fmaf(a0, py, m[5]);
-      m[6] = fmaf(ax, px, m[6]); m[7] = fmaf(ax, py, m[7]); m[8] = fmaf(ay, py, m[8]);
+#pragma unroll
+      for (int k = 0; k < 9; ++k) m[k] = fmaf(f[j], tb->rowmf[j][k], m[k]);
     }
   }
   double md[9];

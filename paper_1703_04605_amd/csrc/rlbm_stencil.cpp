@@ -448,24 +448,30 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
     tab->fp0[j] = (float)pj[j][0];
     tab->fpx[j] = (float)pj[j][1];
     tab->fpy[j] = (float)pj[j][2];
+    // In the FP16 mode the kernels work on the stored ratios h_j = d_j / f^ref_j,
+    // so the float rows carry the class's scale: equilibrium coefficients are
+    // divided by f^ref_j and moment monomials multiplied by it.
+    const bool ratio = d->precision == RLBM_FP16_DEV;
+    const ld fref = ratio ? (ld)tab->scale[j] : 1.0L;
     for (int k = 0; k < RLBM_NB; ++k) {
       tab->M[k][j] = (double)Mld[j][k];
       tab->Mf[k][j] = (float)Mld[j][k];
-      tab->rowf[j][k] = (float)Mld[j][k];
+      tab->rowf[j][k] = (float)(Mld[j][k] / fref);
       tab->rowd[j][k] = (double)Mld[j][k];
     }
     tab->rowf[j][RLBM_R_NX] = tab->fnx[j];
     tab->rowf[j][RLBM_R_NY] = tab->fny[j];
-    tab->rowf[j][RLBM_R_P0] = tab->fp0[j];
-    tab->rowf[j][RLBM_R_PX] = tab->fpx[j];
-    tab->rowf[j][RLBM_R_PY] = tab->fpy[j];
-    tab->rowf[j][RLBM_R_SCALE] = tab->scale[j];
     tab->rowf[j][RLBM_R_INVSCALE] = tab->inv_scale[j];
     tab->rowd[j][RLBM_R_NX] = tab->dnx[j];
     tab->rowd[j][RLBM_R_NY] = tab->dny[j];
-    tab->rowd[j][RLBM_R_P0] = tab->p0[j];
-    tab->rowd[j][RLBM_R_PX] = tab->px[j];
-    tab->rowd[j][RLBM_R_PY] = tab->py[j];
+    // moment monomials p^a p^b, products taken in long double
+    const ld p0 = pj[j][0], px = pj[j][1], py = pj[j][2];
+    const ld mono[9] = {p0, px, py, p0 * p0, p0 * px, p0 * py, px * px, px * py, py * py};
+    for (int a = 0; a < 9; ++a) {
+      tab->rowmf[j][a] = (float)(mono[a] * fref);
+      tab->rowmd[j][a] = (double)mono[a];
+    }
+    tab->rowmf[j][RLBM_RM_SCALE] = tab->scale[j];
   }
   return RLBM_OK;
 }

@@ -13,9 +13,14 @@
 #define RLBM_EOS_NOCT 28
 #define RLBM_EOS_DEG 14
 
-#define RLBM_ROWF 18
-#define RLBM_ROWD 16
-enum { RLBM_R_NX = 10, RLBM_R_NY, RLBM_R_P0, RLBM_R_PX, RLBM_R_PY, RLBM_R_SCALE, RLBM_R_INVSCALE };
+// equilibrium rows: M_j0 .. M_j9, n_x, n_y [, 1/scale] (padded: one wide load)
+#define RLBM_ROWF 16
+#define RLBM_ROWD 12
+enum { RLBM_R_NX = 10, RLBM_R_NY = 11, RLBM_R_INVSCALE = 12 };
+// moment rows: p0, px, py, p0 p0, p0 px, p0 py, px px, px py, py py [, scale]
+#define RLBM_ROWMF 12
+#define RLBM_ROWMD 10
+#define RLBM_RM_SCALE 9
 
 #define RLBM_LANDAU_NEWTON 0      // Newton on det(lambda I - T eta) from lambda = T^00
 #define RLBM_LANDAU_FIXED_POINT 1 // eps = T^00 - T^0i u_i, u_i = (T^0i - T^ij u_j)/eps
@@ -58,11 +63,15 @@ struct RlbmTable {
   float Mf[RLBM_NB][RLBM_QMAX];
   float scale[RLBM_QMAX], inv_scale[RLBM_QMAX];  // FP16: d_j = scale_j * h_j
   double eos[RLBM_EOS_NOCT * 4][RLBM_EOS_DEG];     // inverse EOS pieces
-  // Per-class rows read by the step kernel with one wide scalar load each:
-  // [M_j0 .. M_j9, n_x, n_y, p^0, p^x, p^y, scale, 1/scale, 0] (float) and
-  // [M_j0 .. M_j9, n_x, n_y, p^0, p^x, p^y, 0] (double).
-  float rowf[RLBM_QMAX][RLBM_ROWF];
-  double rowd[RLBM_QMAX][RLBM_ROWD];
+  // Per-class equilibrium rows read by the step kernel with wide scalar loads:
+  // [M_j0 .. M_j9, n_x, n_y, 1/scale, 0, 0, 0] (float) and
+  // [M_j0 .. M_j9, n_x, n_y] (double).
+  float rowf[RLBM_QMAX][RLBM_ROWF] __attribute__((aligned(64)));
+  double rowd[RLBM_QMAX][RLBM_ROWD] __attribute__((aligned(64)));
+  // Per-class moment rows: the nine monomials p^a p^b of eq.
+  // mj-discrete-second-moment (and the FP16 scale), one wide scalar load each.
+  float rowmf[RLBM_QMAX][RLBM_ROWMF] __attribute__((aligned(64)));
+  double rowmd[RLBM_QMAX][RLBM_ROWMD] __attribute__((aligned(64)));
 };
 
 // Per-block health / statistics slot, accumulated by the step kernel.
@@ -72,12 +81,17 @@ struct RlbmSlot {
   uint64_t iter_sum;
 };
 
-// Storage of one population plane: (ny + 2 GY) rows of W elements; site
-// (x, y) lives at (y + GY) W + x + GX.  The ghost columns [-Sx, 0), [nx, nx+Sx)
-// and rows [-Sy, 0), [ny, ny+Sy) hold copies written by the owner sites under
-// the boundary rule, so pulls f_j(x - n_j) need no wrap or clamp.
+// Population storage, row-interleaved: (ny + 2 GY) storage rows, each holding
+// the Q class rows of W elements of one lattice row back to back, so f_j at
+// site (x, y) lives at j cs + (y + GY) rs + x + GX with cs = W and rs = Q W.
+// All classes of a lattice row then share a few hundred KB, and a tile's
+// pulls and stores stay within a few pages.  The ghost columns [-Sx, 0),
+// [nx, nx+Sx) and rows [-Sy, 0), [ny, ny+Sy) hold copies written by the owner
+// sites under the boundary rule, so pulls f_j(x - n_j) need no wrap or clamp.
 struct RlbmLayout {
-  long long plane;  // elements per plane (padded)
+  long long cs;     // elements between classes at one site (W)
+  long long rs;     // elements between storage rows (Q W)
+  long long total;  // elements of the whole buffer (padded)
   int W, GX, GY;
   int nx, ny;
   int Sx, Sy;       // ghost widths actually used (max shifts)
@@ -88,11 +102,14 @@ struct RlbmStepArgs {
   const void* src;
   void* dst;
   RlbmLayout L;
-  const int* offs;     // per class: element offset of the source of f_j relative to
-                       // the site's own storage index in plane 0 (j*plane, minus
-                       // n_y W + n_x when pulling); QMAX entries
+  // Per class, byte offsets from the tile's lowest reachable element (class 0
+  // at (x0 - Sx, y - Sy)): offs = source of f_j (j cs + Sy rs + Sx, minus
+  // n_y rs + n_x when pulling), offs_st = own storage of f_j; QMAX entries each.
+  const unsigned* offs;
+  const unsigned* offs_st;
   int shift;           // 1: pull f_j(x - n_j) (post-collision state), 0: read f_j(x)
-  int blocks_x;        // blocks per row
+  int tiles_x;         // wave tiles (64 sites) per row
+  int ntiles;          // wave tiles of the lattice
   int tau_mode;
   double tau;          // constant tau
   double tk1, tk2;     // eta/s: tau = 1/2 + tk1 (4 - ln(tk2 n / T^3)) / T

@@ -342,13 +342,14 @@ class Solver:
                self.ctx)
 
     def populations(self):
-        """Current state buffer viewed as [q, plane] in storage dtype (layout
-        flag tells whether it is the unstreamed initial state)."""
+        """Current state buffer as a flat tensor in storage dtype: rows of the
+        lattice (with ghost rows), each holding the q class rows of W elements
+        back to back."""
         import numpy as np
         torch = self.torch
         dt = {"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.float16}[self.precision]
         buf = self.pop[0] if (self.step_count() % 2 == 0) else self.pop[1]
-        return buf.view(dt).view(self.info["q"], -1)
+        return buf.view(dt)
 
 
 class Batch:
