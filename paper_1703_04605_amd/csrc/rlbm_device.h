@@ -16,6 +16,27 @@ namespace rlbm {
 typedef const __attribute__((address_space(4))) RlbmTable* TabPtr;
 __device__ __forceinline__ TabPtr as_tab(const RlbmTable* p) { return (TabPtr)p; }
 
+// Quotients of the per-site chain: the hardware reciprocal (and reciprocal
+// square root) refined by two Newton steps, each of which squares the relative
+// error, then one residual correction of the product (a few ulp at most; the
+// operands here are far from the overflow and underflow ranges that the
+// library division guards against).
+__device__ __forceinline__ double rcp_nr(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+__device__ __forceinline__ double div_nr(double a, double d) {
+  const double r = rcp_nr(d);
+  const double q = a * r;
+  return fma(fma(-d, q, a), r, q);
+}
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  return y * fma(-0.5 * x * y, y, 1.5);
+}
+
 // R(z) = K_1(z)/K_2(z), the Bessel ratio of the equation of state
 // (eq. relativistic-eos).  For z < 1.5: the ascending series of K_0 and K_1
 // (integer-order expansions with the logarithmic term, e.g. Abramowitz &
@@ -164,13 +185,13 @@ __device__ __forceinline__ int landau_newton(double T00, double T0x, double T0y,
     const double la = l - T00;
     const double p = fma(la, m, fma(T0x * T0x, pf, fma(T0y * T0y, pd, -bce2)));
     const double dp = fma(la, pd + pf, m + b2c2);
-    const double step = p / dp;
+    const double step = div_nr(p, dp);
     l -= step;
     if (done) break;
     if (fabs(step) <= thresh * l) done = true;
   }
   const double pd = l + Txx, pf = l + Tyy;
-  const double inv = 1.0 / fma(pd, pf, -e2);
+  const double inv = rcp_nr(fma(pd, pf, -e2));
   ux = (T0x * pf - T0y * Txy) * inv;
   uy = (T0y * pd - T0x * Txy) * inv;
   eps = l;
@@ -211,7 +232,7 @@ __device__ __forceinline__ int landau_solve(double T00, double T0x, double T0y, 
 __device__ __forceinline__ void projections(TabPtr tb, double T, double R, double U0, double Ux, double Uy,
                                             double b[RLBM_NB]) {
   const auto& c = tb->c;
-  const double b0 = R / c.zeta;
+  const double b0 = R * c.inv_zeta;
   const double q = fma(c.zeta, R, 4.0 * T);
   b[0] = b0;
   b[1] = (U0 - c.a1 * b0) * c.invA;

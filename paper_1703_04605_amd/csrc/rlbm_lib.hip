@@ -84,6 +84,10 @@ struct Macro {
   unsigned flags;
 };
 
+// Newton stopping threshold for a requested tolerance (the last step is taken
+// after the step falls below it: quadratic convergence)
+__device__ __forceinline__ double newton_thresh(double tol) { return 0.1 * sqrt(tol); }
+
 // guess (eps0, ux0, uy0): starting point of the Landau solve; eps0 <= 0 means
 // none (Newton from T^00, fixed point from u = 0)
 __device__ __forceinline__ Macro macroscopic(TabPtr tb, double N0, double Nx, double Ny,
@@ -96,22 +100,22 @@ __device__ __forceinline__ Macro macroscopic(TabPtr tb, double N0, double Nx, do
   m.ux = guess ? ux0 : 0.0;
   m.uy = guess ? uy0 : 0.0;
   if (method == RLBM_LANDAU_NEWTON)
-    m.iters = landau_newton(T00, T0x, T0y, Txx, Txy, Tyy, 0.1 * sqrt(tol), maxit, m.eps, m.ux, m.uy,
+    m.iters = landau_newton(T00, T0x, T0y, Txx, Txy, Tyy, newton_thresh(tol), maxit, m.eps, m.ux, m.uy,
                             guess ? eps0 : T00);
   else
     m.iters = landau_solve(T00, T0x, T0y, Txx, Txy, Tyy, tol, maxit, m.eps, m.ux, m.uy);
   if (m.iters > maxit) m.flags |= RLBM_H_LANDAU;
   const double u2 = m.ux * m.ux + m.uy * m.uy;
   if (!(u2 < 1.0)) m.flags |= RLBM_H_SUPERLUMINAL;
-  m.gamma = 1.0 / sqrt(1.0 - u2);
+  m.gamma = rsqrt_nr(1.0 - u2);
   m.n = m.gamma * (N0 - m.ux * Nx - m.uy * Ny);
   if (!(m.n > 0.0) || !(m.eps > 0.0)) m.flags |= RLBM_H_RANGE;
   const double zeta = tb->c.zeta;
-  const double e = m.eps / m.n;
+  const double e = div_nr(m.eps, m.n);
   m.T = eos_temperature_tab(tb, e, zeta, m.flags);
   m.P = m.n * m.T;
   // K1/K2 at z = zeta/T from the EOS itself: zeta R = e - 3T
-  m.R = (e - 3.0 * m.T) / zeta;
+  m.R = (e - 3.0 * m.T) * tb->c.inv_zeta;
   if (!isfinite(m.T) || !isfinite(m.eps) || !isfinite(m.n) || !isfinite(m.R)) m.flags |= RLBM_H_NAN;
   return m;
 }
@@ -420,7 +424,7 @@ k_step(RlbmStepArgs a) {
   double b[RLBM_NB];
   projections(tb, mac.T, mac.R, mac.gamma, mac.gamma * mac.ux, mac.gamma * mac.uy, b);
   // Anderson-Witting frequency p_i.U/(p_i^0 tau) = gamma (1 - v0 n_i.u)/tau (eq. discrete-relativistic-boltzmann)
-  const double w0 = mac.gamma / tau;
+  const double w0 = a.tau_mode == RLBM_TAU_CONST ? mac.gamma * a.inv_tau : div_nr(mac.gamma, tau);
   const double wx = -w0 * tb->c.v0 * mac.ux, wy = -w0 * tb->c.v0 * mac.uy;
   A nb[RLBM_NB];
 #pragma unroll
@@ -800,10 +804,9 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   RlbmStepArgs a;
   a.L = c->L;
-  a.tiles_x = c->tiles_x;
-  a.ntiles = c->ntiles;
   a.tau_mode = c->lat.tau_mode;
   a.tau = c->lat.tau;
+  a.inv_tau = 1.0 / c->lat.tau;
   a.tk1 = c->tk1;
   a.tk2 = c->tk2;
   a.landau_tol = c->lat.landau_tol;
@@ -819,6 +822,8 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
     for (int i = 0; i < 9; ++i) a.mlp_norm[9 + i] = 1.0f / c->guess->h_norm[9 + i];
   }
   StepFn fn = select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
+  a.tiles_x = c->tiles_x;
+  a.ntiles = c->ntiles;
   const unsigned nwg = (unsigned)((c->ntiles + kBlock / kWave - 1) / (kBlock / kWave));
   for (int i = 0; i < nsteps; ++i) {
     a.src = c->buf[c->cur];

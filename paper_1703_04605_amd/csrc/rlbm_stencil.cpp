@@ -387,6 +387,7 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
   c.sx_max = sx_max;
   c.sy_max = sy_max;
   c.zeta = d->zeta;
+  c.inv_zeta = (double)(1.0L / (ld)d->zeta);
   c.v0 = (double)v0;
   c.a1 = (double)B.a1;
   c.invA = (double)(1.0L / B.A);

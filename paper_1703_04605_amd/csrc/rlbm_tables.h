@@ -38,6 +38,7 @@ struct RlbmConsts {
   int max_shift;
   int sx_max, sy_max;  // max |n_x|, max |n_y| over the classes
   double zeta;    // mbar = m / T_R
+  double inv_zeta;
   double v0;
   // Appendix A constants at mbar (T_R = 1):
   double a1;      // mbar K2/K1        (J^(1)_0 offset)
@@ -112,6 +113,7 @@ struct RlbmStepArgs {
   int ntiles;          // wave tiles of the lattice
   int tau_mode;
   double tau;          // constant tau
+  double inv_tau;      // 1 / tau
   double tk1, tk2;     // eta/s: tau = 1/2 + tk1 (4 - ln(tk2 n / T^3)) / T
   double landau_tol;
   int landau_maxit;
