@@ -23,7 +23,7 @@ HBM_PEAK_GBS = 8000.0
 ELEM = {"fp64": 8, "fp32": 4, "fp16": 2}
 STEP_KERNEL_SOURCES = ["paper_1703_04605_amd/csrc/rlbm_lib.hip", "paper_1703_04605_amd/csrc/rlbm_device.h",
                        "paper_1703_04605_amd/csrc/rlbm_tables.h", "paper_1703_04605_amd/csrc/rlbm_mlp.h",
-                       "paper_1703_04605_amd/csrc/bessel_ratio_coeffs.h"]
+                       "paper_1703_04605_amd/csrc/bessel_ratio_coeffs.h", "paper_1703_04605_amd/csrc/gen_fixed_stencils.cpp"]
 
 
 def kernel_source_hash():
@@ -46,11 +46,12 @@ def measured_traffic(precision, nx, ny):
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
-def time_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton", guess=None):
+def time_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton", guess=None, variant="auto"):
     import torch
     from paper_1703_04605_amd import rlbm
     s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=2, precision=precision)
     s.init_fields(*fields, tau=tau, landau=landau)
+    s.set_step_variant(variant)
     if guess is not None:
         s.set_landau_guess(guess)
     s.step(warmup)
@@ -191,24 +192,26 @@ def main():
     traffic = measured_traffic(args.precision, nx, ny)
     out_hp = {k: v.cpu().numpy() for k, v in s.moments().items()}
     iters_mean = h["iter_sum"] / (sites * args.steps)
+    kernel = s.step_kernel()
     del s
 
     paths = {args.precision: {"mlups": mlups, "ms_per_step": ms_step, "hbm_frac": achieved / HBM_PEAK_GBS,
                               "landau_iter_mean": iters_mean, "landau_iter_max": h["iter_max"],
-                              "health_flags": h["flags"]}}
+                              "health_flags": h["flags"], "kernel": kernel}}
     if not args.no_compare:
-        for key in ("fp64", "fp32", "fp16", "fp64_fixed_point", "fp32_fixed_point"):
+        for key in ("fp64", "fp32", "fp16", "fp64_fixed_point", "fp32_fixed_point", "fp32_table", "fp16_table"):
             p = key.split("_")[0]
             landau = "fixed_point" if key.endswith("fixed_point") else "newton"
+            variant = "table" if key.endswith("table") else "auto"
             if key == args.precision:
                 continue
-            s2, ms2, _, h2 = time_path(st, fields, p, args.steps, args.warmup, landau=landau)
+            s2, ms2, _, h2 = time_path(st, fields, p, args.steps, args.warmup, landau=landau, variant=variant)
             m2 = sites * args.steps / (ms2 * 1e-3) / 1e6
             ab = 2 * q * ELEM[p] * sites / (ms2 / args.steps * 1e-3) / 1e9
             o2 = {k: v.cpu().numpy() for k, v in s2.moments().items()}
             paths[key] = {"mlups": m2, "ms_per_step": ms2 / args.steps, "hbm_frac": ab / HBM_PEAK_GBS,
                         "landau_iter_mean": h2["iter_sum"] / (sites * args.steps),
-                        "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"]}
+                        "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"], "kernel": s2.step_kernel()}
             if key == "fp64":
                 # deviation of the headline path from the float64 GPU path (itself
                 # parity-tested against the oracle) after the full horizon
@@ -227,14 +230,22 @@ def main():
             o2 = {k: v.cpu().numpy() for k, v in s2.moments().items()}
             paths[key] = {"mlups": m2, "ms_per_step": ms2 / args.steps, "hbm_frac": ab / HBM_PEAK_GBS,
                           "landau_iter_mean": h2["iter_sum"] / (sites * args.steps),
-                          "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"]}
+                          "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"],
+                          "kernel": s2.step_kernel()}
+            # the same step kernel without the guess (the guided kernel is the
+            # table-driven one), and the fastest unguided path of this method
+            s3, ms3, _, h3 = time_path(st, fields, "fp32", args.steps, args.warmup, landau=landau, variant="table")
+            m3 = sites * args.steps / (ms3 * 1e-3) / 1e6
+            o3 = {k: v.cpu().numpy() for k, v in s3.moments().items()}
+            del s3
+            paths[key]["unguided_same_kernel_mlups"] = m3
+            paths[key]["unguided_same_kernel_landau_iter_mean"] = h3["iter_sum"] / (sites * args.steps)
+            paths[key]["speedup_vs_unguided_same_kernel"] = m2 / m3
+            paths[key]["max_rel_err_vs_unguided_same_kernel"] = {
+                k: float(np.abs(o2[k] - o3[k]).max() / np.abs(o3[k]).max()) for k in ("n", "eps", "T", "P", "ux", "uy")}
             ref_key = "fp32" if landau == "newton" else "fp32_fixed_point"
             if ref_key == args.precision or ref_key in paths:
-                paths[key]["speedup_vs_unguided"] = m2 / paths[ref_key]["mlups"]
-            if landau == "newton" and args.precision == "fp32":
-                paths[key]["max_rel_err_vs_unguided"] = {
-                    k: float(np.abs(o2[k] - out_hp[k]).max() / np.abs(out_hp[k]).max())
-                    for k in ("n", "eps", "T", "P", "ux", "uy")}
+                paths[key]["speedup_vs_fastest_unguided"] = m2 / paths[ref_key]["mlups"]
             if "fp64" in paths:
                 paths[key]["speedup_vs_fp64"] = m2 / paths["fp64"]["mlups"]
             del s2

@@ -211,6 +211,27 @@ int rlbm_get_health(rlbm_ctx* ctx, unsigned* flags, unsigned long long* landau_i
 /* Completed time steps since rlbm_init_fields. */
 long long rlbm_step_count(const rlbm_ctx* ctx);
 
+/*
+ * Step kernel selection.  The same time step (Sec. III, eqs. mj-discrete-feq
+ * and discrete-relativistic-boltzmann) is available in two forms: the
+ * table-driven kernel, which reads each class's moment and equilibrium rows
+ * from the stencil table, and, for the stencils of the configured workloads
+ * in float32 and float16 storage, a kernel compiled with those rows as
+ * constants and the class loops factored by the square's symmetry (built by
+ * gen_fixed_stencils.cpp from the library's own table builder; used only when
+ * the context's table matches bit for bit).  Both compute the same
+ * arithmetic up to rounding order.
+ * rlbm_set_step_variant: RLBM_STEP_AUTO (default: the fixed-stencil kernel
+ * when one matches) or RLBM_STEP_TABLE (always the table-driven kernel);
+ * RLBM_EINVAL on other values.  rlbm_step_kernel: which kernel the next
+ * rlbm_step runs (RLBM_STEP_TABLE or RLBM_STEP_FIXED); RLBM_EINVAL for NULL.
+ */
+#define RLBM_STEP_AUTO 0
+#define RLBM_STEP_TABLE 1
+#define RLBM_STEP_FIXED 2
+int rlbm_set_step_variant(rlbm_ctx* ctx, int variant);
+int rlbm_step_kernel(const rlbm_ctx* ctx);
+
 /* Copies the current state (population buffer in storage precision, as laid
  * out by the library) to dst (device or host, pop_bytes) and back; with the
  * step count this is the whole state (checkpoint / resume). */

@@ -20,10 +20,15 @@ def build(verbose=False):
     host_obj = os.path.join(HERE, "_build", "rlbm_stencil.o")
     dev_obj = os.path.join(HERE, "_build", "rlbm_lib.o")
     mlp_obj = os.path.join(HERE, "_build", "rlbm_mlp.o")
+    gen_exe = os.path.join(HERE, "_build", "gen_fixed_stencils")
+    gen_hdr = os.path.join(HERE, "_build", "rlbm_fixed_stencils.h")
     cmds = [
         ["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-c", os.path.join(CSRC, "rlbm_stencil.cpp"), "-o", host_obj],
+        # fixed-stencil class code, generated from the library's own table builder
+        ["g++", "-O2", "-std=c++17", "-Wall", os.path.join(CSRC, "gen_fixed_stencils.cpp"), host_obj, "-o", gen_exe],
+        [gen_exe, gen_hdr],
         [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "rlbm_mlp.hip"), "-o", mlp_obj],
-        [HIPCC] + HIP_FLAGS + ["-c", os.path.join(CSRC, "rlbm_lib.hip"), "-o", dev_obj],
+        [HIPCC] + HIP_FLAGS + ["-I", os.path.join(HERE, "_build"), "-c", os.path.join(CSRC, "rlbm_lib.hip"), "-o", dev_obj],
         [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", dev_obj, mlp_obj, host_obj, "-o", LIB + ".tmp"],
     ]
     for cmd in cmds:

@@ -16,6 +16,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <vector>
 
@@ -24,6 +25,7 @@
 #include "rlbm_mlp.h"
 #include "rlbm_stencil.h"
 #include "rlbm_tables.h"
+#include "rlbm_fixed_stencils.h"  // generated at build time
 
 namespace rlbm {
 
@@ -325,6 +327,22 @@ __device__ __forceinline__ R load_row(const __attribute__((address_space(4))) R*
   return r;
 }
 
+// Store of the post-collision value of class J for the fixed-stencil class
+// code (float32 or float16 storage).
+template <int P>
+struct TileStore {
+  __amdgpu_buffer_rsrc_t r;
+  int vst;
+  const __attribute__((address_space(4))) unsigned* own;
+  template <int J>
+  __device__ __forceinline__ void put(float v) {
+    if constexpr (P == RLBM_FP32_DEV)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vst, own[J], 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, vst, own[J], 0);
+  }
+};
+
 // One time step for one tile per wave (kWave consecutive sites of a row), for
 // a stencil of QMIN..QN classes.  The class loops are fully unrolled, so the
 // populations stay in registers.
@@ -342,9 +360,10 @@ __device__ __forceinline__ R load_row(const __attribute__((address_space(4))) R*
 // class j is processed (scalar loads complete in any order, so every wait is
 // for all of them).  In the FP16 mode the rows carry the per-class scale, so
 // the kernel relaxes the stored ratios h_j = (f_j - f^ref_j) / f^ref_j directly.
-template <int QN, int QMIN, int P, bool G>
+template <int QN, int QMIN, int P, bool G, class Fx = void>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves(QN, P, G))))
 k_step(RlbmStepArgs a) {
+  constexpr bool kFixed = !std::is_same<Fx, void>::value;
   using S = typename Traits<P>::S;
   using A = typename Traits<P>::A;
   typedef const __attribute__((address_space(4))) unsigned* OffPtr;
@@ -388,7 +407,11 @@ k_step(RlbmStepArgs a) {
   // monomial; deviation modes add the exact float64 moments of the reference
   A f[QN];
   A m[9] = {A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0)};
-  {
+  if constexpr (kFixed) {
+#pragma unroll
+    for (int j = 0; j < QN; ++j) f[j] = (A)raw[j];
+    Fx::moments(f, m);
+  } else {
     const auto* rows = Rows<P>::m(tb);
     typename Rows<P>::M cur = load_row(rows);
 #pragma unroll
@@ -432,7 +455,10 @@ k_step(RlbmStepArgs a) {
   const A W0 = (A)w0, WX = (A)wx, WY = (A)wy;
 
   // equilibrium (eq. mj-discrete-feq) and relaxation, stored at the own site
-  {
+  if constexpr (kFixed) {
+    TileStore<P> st{rs_st, vst, own};
+    Fx::collide(f, nb, W0, WX, WY, st);
+  } else {
     const auto* rows = Rows<P>::e(tb);
     typename Rows<P>::E cur = load_row(rows);
 #pragma unroll
@@ -555,6 +581,19 @@ StepFn step_kernel(int Q) {
   return k_step<160, 81, P, G>;
 }
 
+// Generated fixed-stencil kernels, by id (see rlbm_fixed_stencils.h).
+StepFn fixed_step(int id) {
+  switch (id) {
+#define RLBM_FIXED_CASE(ID, ST, PREC) \
+  case ID:                            \
+    return k_step<rlbm_fixed::ST::Q, rlbm_fixed::ST::Q, PREC, false, rlbm_fixed::ST>;
+    RLBM_FIXED_KERNELS(RLBM_FIXED_CASE)
+#undef RLBM_FIXED_CASE
+    default:
+      return nullptr;
+  }
+}
+
 // The learned-guess kernels are built for float32 storage, the path the
 // guess is meant for.
 StepFn select_step(int prec, int Q, bool guess) {
@@ -627,6 +666,8 @@ struct rlbm_ctx {
   int nslots = 0;               // health slots: one per tile
   double tk1 = 0, tk2 = 0;
   const rlbm_mlp* guess = nullptr;
+  int fixed_id = -1;                // generated fixed-stencil kernel for this table, or -1
+  int variant = RLBM_STEP_AUTO;     // RLBM_STEP_AUTO or RLBM_STEP_TABLE
   char err[512] = {0};
 };
 
@@ -658,6 +699,12 @@ extern "C" int rlbm_init_stencil(rlbm_ctx** out, const rlbm_stencil_desc* desc, 
     return rc;
   }
   rlbm_build_eos_table(desc->zeta, c->h_tab->eos);
+  // a generated fixed-stencil kernel applies when this table is the one it was generated from
+  c->fixed_id = -1;
+  const uint64_t fp = rlbm_table_fingerprint(c->h_tab);
+  for (int i = 0; i < rlbm_fixed::kNumFixed; ++i)
+    if (rlbm_fixed::kFixedTables[i].fingerprint == fp && rlbm_fixed::kFixedTables[i].precision == c->h_tab->c.precision)
+      c->fixed_id = i;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->d_tab, sizeof(RlbmTable));
   if (e == hipSuccess) e = hipMemcpy(c->d_tab, c->h_tab, sizeof(RlbmTable), hipMemcpyHostToDevice);
@@ -821,7 +868,9 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
     for (int i = 0; i < 24; ++i) a.mlp_norm[i] = c->guess->h_norm[i];
     for (int i = 0; i < 9; ++i) a.mlp_norm[9 + i] = 1.0f / c->guess->h_norm[9 + i];
   }
-  StepFn fn = select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
+  StepFn fn = (!g && c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? fixed_step(c->fixed_id)
+                                                                       : select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
+  if (!fn) return fail(c, RLBM_ESTATE, "no step kernel for this stencil");
   a.tiles_x = c->tiles_x;
   a.ntiles = c->ntiles;
   const unsigned nwg = (unsigned)((c->ntiles + kBlock / kWave - 1) / (kBlock / kWave));
@@ -892,6 +941,19 @@ extern "C" int rlbm_get_health(rlbm_ctx* c, unsigned* flags, unsigned long long*
 }
 
 extern "C" long long rlbm_step_count(const rlbm_ctx* c) { return c ? c->steps : -1; }
+
+extern "C" int rlbm_set_step_variant(rlbm_ctx* c, int variant) {
+  if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
+  if (variant != RLBM_STEP_AUTO && variant != RLBM_STEP_TABLE) return fail(c, RLBM_EINVAL, "invalid step variant");
+  c->variant = variant;
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_step_kernel(const rlbm_ctx* c) {
+  if (!c) return RLBM_EINVAL;
+  const bool g = c->guess != nullptr && c->h_tab->c.precision == RLBM_FP32_DEV;
+  return (!g && c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? RLBM_STEP_FIXED : RLBM_STEP_TABLE;
+}
 
 extern "C" int rlbm_save_state(rlbm_ctx* c, void* dst, size_t bytes, long long* step, int* layout_flag,
                                void* stream) {

@@ -477,6 +477,28 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
   return RLBM_OK;
 }
 
+uint64_t rlbm_table_fingerprint(const RlbmTable* t) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  };
+  const int Q = t->c.Q;
+  mix(&t->c.Q, sizeof(int));
+  mix(&t->c.dim, sizeof(int));
+  mix(&t->c.precision, sizeof(int));
+  mix(t->nx, sizeof(int) * Q);
+  mix(t->ny, sizeof(int) * Q);
+  for (int j = 0; j < Q; ++j) {
+    mix(t->rowmf[j], sizeof(float) * 9);
+    mix(t->rowf[j], sizeof(float) * RLBM_NB);
+  }
+  return h;
+}
+
 static thread_local char g_err[512];
 
 extern "C" int rlbm_solve_stencil(const rlbm_stencil_desc* desc, rlbm_stencil_info* info) {

@@ -1,6 +1,7 @@
 // Host-side stencil construction shared by the library's entry points.
 #pragma once
 #include <stddef.h>
+#include <stdint.h>
 
 #include "../../include/rlbm.h"
 #include "rlbm_tables.h"
@@ -11,6 +12,11 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
                      size_t errlen);
 const char* rlbm_global_error();
 void rlbm_set_global_error(const char* msg);
+
+// 64-bit FNV-1a fingerprint of the parts of a class table that the fixed-
+// stencil kernels compile in (class count, dimension, precision, class
+// displacements, float moment and equilibrium rows).
+uint64_t rlbm_table_fingerprint(const RlbmTable* t);
 
 // Chebyshev pieces of the inverse equation of state T(u)/u for mbar = zeta
 // (layout of RlbmTable::eos).

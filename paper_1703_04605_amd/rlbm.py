@@ -33,7 +33,9 @@ EXPORTS = ["rlbm_init_stencil", "rlbm_solve_stencil", "rlbm_class_table", "rlbm_
            "rlbm_mlp_train_step", "rlbm_mlp_predict", "rlbm_mlp_get_params", "rlbm_set_landau_guess",
            "rlbm_landau_guess_fields", "rlbm_batch_create", "rlbm_batch_destroy", "rlbm_batch_population_bytes",
            "rlbm_batch_sites", "rlbm_batch_init", "rlbm_batch_step_persistent", "rlbm_batch_moments",
-           "rlbm_batch_get_health"]
+           "rlbm_batch_get_health", "rlbm_set_step_variant", "rlbm_step_kernel"]
+
+STEP_AUTO, STEP_TABLE, STEP_FIXED = 0, 1, 2
 
 
 class RlbmError(RuntimeError):
@@ -94,6 +96,10 @@ def lib():
                                   ctypes.POINTER(ctypes.c_uint), ci, vp]
     L.rlbm_step_count.argtypes = [vp]
     L.rlbm_step_count.restype = ctypes.c_longlong
+    L.rlbm_set_step_variant.argtypes = [vp, ci]
+    L.rlbm_set_step_variant.restype = ci
+    L.rlbm_step_kernel.argtypes = [vp]
+    L.rlbm_step_kernel.restype = ci
     L.rlbm_save_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_longlong),
                                   ctypes.POINTER(ctypes.c_int), vp]
     L.rlbm_load_state.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_longlong, ci, vp]
@@ -327,6 +333,15 @@ class Solver:
 
     def step_count(self):
         return lib().rlbm_step_count(self.ctx)
+
+    def set_step_variant(self, variant):
+        """"auto" (the generated fixed-stencil kernel when one matches this
+        stencil) or "table" (always the table-driven kernel)."""
+        _check(lib().rlbm_set_step_variant(self.ctx, {"auto": STEP_AUTO, "table": STEP_TABLE}[variant]), self.ctx)
+
+    def step_kernel(self):
+        """Which kernel the next step runs: "table" or "fixed"."""
+        return {STEP_TABLE: "table", STEP_FIXED: "fixed"}[lib().rlbm_step_kernel(self.ctx)]
 
     def save_state(self):
         torch = self.torch

@@ -111,7 +111,9 @@ def test_in_step_inference_matches_oracle():
 @pytest.mark.parametrize("landau", ["newton", "fixed_point"])
 def test_guided_step_matches_plain_and_saves_iterations(landau):
     """With a trained network the fields equal the unguided run's to 1e-6 and
-    the Landau solve takes fewer iterations."""
+    the Landau solve takes fewer iterations.  Both runs use the table-driven
+    step kernel (the guided kernel is built on it), so the comparison sees the
+    guess's effect only, not the rounding order of the fixed-stencil kernel."""
     from paper_1703_04605_amd import rlbm, learned_guess
     from tests.helpers import field_errors
     raw9, target = moment_batch(8192, seed=4)
@@ -125,8 +127,10 @@ def test_guided_step_matches_plain_and_saves_iterations(landau):
     for guided in (False, True):
         s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], precision="fp32")
         s.init_fields(*fields, tau=0.9, landau=landau)
+        s.set_step_variant("table")
         if guided:
             s.set_landau_guess(net)
+        assert s.step_kernel() == "table"
         s.step(30)
         h = s.health()
         res[guided] = ({k: v.cpu().numpy() for k, v in s.moments().items()}, h["iter_sum"] / (128 * 128 * 30))
