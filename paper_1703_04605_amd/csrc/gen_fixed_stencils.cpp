@@ -11,17 +11,19 @@
 // The merged in-plane classes of a stencil built from full-symmetric groups
 // fall into orbits of the square's symmetry group D4: {(0,0)}, the 4 classes
 // (+-a, 0), (0, +-a), the 4 classes (+-a, +-a) and the 8 classes (+-a, +-b),
-// (+-b, +-a), each with one energy p^0.  With the orbit's members ordered so
-// that the bits of a member's index are its x sign, y sign and x<->y swap,
-// the Sylvester-Hadamard matrix H (H H = n I) block-diagonalises the rows:
-// R_orbit = H C with C = H R_orbit / n sparse (symmetry zeros).  So
+// (+-b, +-a), each with one energy p^0.  Within an orbit, sums and differences
+// of member values (butterflies x + y, x - y) separate the symmetry classes of
+// the rows, after which most row coefficients vanish.  For a transform T made
+// of butterflies (on member pairs of the fast Walsh-Hadamard stages, each pair
+// used or not), R_orbit = T^T C with C = (T^T)^-1 R_orbit, and
 //
-//   moments:      B = H f_orbit (fast Walsh-Hadamard transform), m_k += C_ok B_o
-//   equilibrium:  g = C' nb, f^eq_orbit = H g
+//   moments:      B = T f_orbit, m_k += C_ok B_o
+//   equilibrium:  g = C' nb, f^eq_orbit = T^T g   (butterflies in reverse order)
 //
-// for the nonzero entries only.  Entries whose magnitude is below 1e-12 of the
-// orbit's rows are symmetry zeros; the generator checks that H C reproduces
-// the rows to that accuracy and otherwise treats the orbit's classes one by one.
+// for the nonzero entries only.  Entries below 1e-12 of the orbit's largest
+// row entry are symmetry zeros; every transform is checked to reproduce the
+// rows to that accuracy, and the cheapest one (additions plus multiply-adds)
+// is chosen, separately for the moments and for the equilibrium.
 //
 // The output also carries each stencil's table fingerprint; the library uses
 // a generated kernel only for a context whose table has the same fingerprint.
@@ -109,17 +111,6 @@ static std::string flit(ld x) {
   return b;
 }
 
-static void hadamard(int n, std::vector<std::vector<int>>& H) {
-  H.assign(n, std::vector<int>(n, 1));
-  for (int h = 1; h < n; h *= 2)
-    for (int i = 0; i < h; ++i)
-      for (int j = 0; j < h; ++j) {
-        H[i][j + h] = H[i][j];
-        H[i + h][j] = H[i][j];
-        H[i + h][j + h] = -H[i][j];
-      }
-}
-
 // Orbits of the classes: lists of class indices in canonical member order.
 static std::vector<std::vector<int>> orbits(const RlbmTable& t) {
   const int Q = t.c.Q;
@@ -149,77 +140,176 @@ static std::vector<std::vector<int>> orbits(const RlbmTable& t) {
   return res;
 }
 
-// C = H R / n for the orbit; returns false if H C does not reproduce R.
-static bool factor(const std::vector<std::vector<ld>>& R, std::vector<std::vector<ld>>& C) {
+typedef std::vector<std::pair<int, int>> Bfly;  // butterflies (i, j): (x_i, x_j) <- (x_i + x_j, x_i - x_j)
+
+// Candidate transforms of an n-member orbit: every subset of the pairs of the
+// fast Walsh-Hadamard stages (in stage order).
+static std::vector<Bfly> candidates(int n) {
+  std::vector<std::pair<int, int>> pairs;
+  for (int h = 1; h < n; h *= 2)
+    for (int i = 0; i < n; i += 2 * h)
+      for (int j = i; j < i + h; ++j) pairs.push_back({j, j + h});
+  std::vector<Bfly> res;
+  const int np = (int)pairs.size();
+  for (int mask = 0; mask < (1 << np); ++mask) {
+    Bfly b;
+    for (int p = 0; p < np; ++p)
+      if (mask >> p & 1) b.push_back(pairs[p]);
+    res.push_back(b);
+  }
+  return res;
+}
+
+// T (n x n) of a butterfly sequence: B = T x.
+static std::vector<std::vector<ld>> tmatrix(int n, const Bfly& b) {
+  std::vector<std::vector<ld>> T(n, std::vector<ld>(n, 0));
+  for (int i = 0; i < n; ++i) T[i][i] = 1;
+  for (auto& p : b)
+    for (int c = 0; c < n; ++c) {
+      const ld x = T[p.first][c], y = T[p.second][c];
+      T[p.first][c] = x + y;
+      T[p.second][c] = x - y;
+    }
+  return T;
+}
+
+// C solving T^T C = R (Gaussian elimination with partial pivoting, long
+// double), symmetry zeros cleared; false if the result does not reproduce R.
+static bool solve_rows(const std::vector<std::vector<ld>>& T, const std::vector<std::vector<ld>>& R,
+                       std::vector<std::vector<ld>>& C) {
   const int n = (int)R.size(), K = (int)R[0].size();
-  std::vector<std::vector<int>> H;
-  hadamard(n, H);
+  std::vector<std::vector<ld>> A(n, std::vector<ld>(n + K));
+  for (int i = 0; i < n; ++i) {
+    for (int o = 0; o < n; ++o) A[i][o] = T[o][i];
+    for (int k = 0; k < K; ++k) A[i][n + k] = R[i][k];
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (fabsl(A[r][c]) > fabsl(A[piv][c])) piv = r;
+    if (fabsl(A[piv][c]) < 1e-30L) return false;
+    std::swap(A[c], A[piv]);
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const ld f = A[r][c] / A[c][c];
+      for (int q = c; q < n + K; ++q) A[r][q] -= f * A[c][q];
+    }
+  }
   ld mx = 0;
   for (auto& r : R)
     for (ld v : r) mx = std::max(mx, fabsl(v));
   C.assign(n, std::vector<ld>(K, 0));
   for (int o = 0; o < n; ++o)
     for (int k = 0; k < K; ++k) {
-      ld s = 0;
-      for (int i = 0; i < n; ++i) s += H[o][i] * R[i][k];
-      s /= n;
-      C[o][k] = fabsl(s) <= 1e-12L * mx ? 0 : s;
+      const ld v = A[o][n + k] / A[o][o];
+      C[o][k] = fabsl(v) <= 1e-12L * mx ? 0 : v;
     }
   for (int i = 0; i < n; ++i)
     for (int k = 0; k < K; ++k) {
       ld s = 0;
-      for (int o = 0; o < n; ++o) s += H[o][i] * C[o][k];
+      for (int o = 0; o < n; ++o) s += T[o][i] * C[o][k];
       if (fabsl(s - R[i][k]) > 1e-12L * (mx > 0 ? mx : 1)) return false;
     }
   return true;
 }
 
+static int nnz(const std::vector<ld>& r) {
+  int c = 0;
+  for (ld v : r) c += v != 0;
+  return c;
+}
+
+// Operations of the equilibrium side: row products of g, then the reversed
+// butterflies on g with symbolic zeros.
+static int eq_cost(const std::vector<std::vector<ld>>& C, const Bfly& b) {
+  const int n = (int)C.size();
+  int ops = 0;
+  std::vector<bool> nz(n);
+  for (int o = 0; o < n; ++o) {
+    const int k = nnz(C[o]);
+    nz[o] = k > 0;
+    ops += k;
+  }
+  for (int i = (int)b.size() - 1; i >= 0; --i) {
+    const int x = b[i].first, y = b[i].second;
+    if (nz[x] && nz[y]) ops += 2;
+    nz[x] = nz[y] = nz[x] || nz[y];
+  }
+  return ops;
+}
+
+struct OrbitPlan {
+  std::vector<int> members;
+  Bfly bm, be;                           // transforms of the moment and equilibrium sides
+  std::vector<std::vector<ld>> Cm, Ce;   // coefficients
+};
+
+static OrbitPlan plan_orbit(const RlbmTable& t, const std::vector<int>& o) {
+  const int n = (int)o.size();
+  std::vector<std::vector<ld>> Rm, Re;
+  for (int j : o) {
+    std::vector<ld> rm(9), re(RLBM_NB);
+    for (int k = 0; k < 9; ++k) rm[k] = t.rowmf[j][k];
+    for (int k = 0; k < RLBM_NB; ++k) re[k] = t.rowf[j][k];
+    Rm.push_back(rm);
+    Re.push_back(re);
+  }
+  OrbitPlan pl;
+  pl.members = o;
+  int best_m = 1 << 30, best_e = 1 << 30;
+  for (const Bfly& b : candidates(n)) {
+    const auto T = tmatrix(n, b);
+    std::vector<std::vector<ld>> C;
+    if (solve_rows(T, Rm, C)) {
+      int cost = 2 * (int)b.size();
+      for (auto& r : C) cost += nnz(r);
+      if (cost < best_m) {
+        best_m = cost;
+        pl.bm = b;
+        pl.Cm = C;
+      }
+    }
+    if (solve_rows(T, Re, C)) {
+      const int cost = eq_cost(C, b);
+      if (cost < best_e) {
+        best_e = cost;
+        pl.be = b;
+        pl.Ce = C;
+      }
+    }
+  }
+  return pl;
+}
+
 static std::string gen_struct(const char* sname, const RlbmTable& t) {
   const int Q = t.c.Q;
-  const auto orb0 = orbits(t);
-  // orbits that factor; others split into single classes
-  std::vector<std::vector<int>> orb;
-  for (auto& o : orb0) {
-    std::vector<std::vector<ld>> Rm, Re, Cm, Ce;
-    for (int j : o) {
-      std::vector<ld> rm(9), re(RLBM_NB);
-      for (int k = 0; k < 9; ++k) rm[k] = t.rowmf[j][k];
-      for (int k = 0; k < RLBM_NB; ++k) re[k] = t.rowf[j][k];
-      Rm.push_back(rm);
-      Re.push_back(re);
-    }
-    if (factor(Rm, Cm) && factor(Re, Ce)) orb.push_back(o);
-    else
-      for (int j : o) orb.push_back({j});
-  }
+  std::vector<OrbitPlan> plans;
+  for (auto& o : orbits(t)) plans.push_back(plan_orbit(t, o));
   Emitter em;
   std::string s;
   s += "struct " + std::string(sname) + " {\n";
   s += "  static constexpr int Q = " + std::to_string(Q) + ";\n";
-  s += "  static constexpr int orbits = " + std::to_string(orb.size()) + ";\n";
+  s += "  static constexpr int orbits = " + std::to_string(plans.size()) + ";\n";
   // moments
   em.out.clear();
-  for (auto& o : orb) {
-    const int n = (int)o.size();
-    std::vector<std::vector<ld>> R, C;
-    for (int j : o) {
-      std::vector<ld> r(9);
-      for (int k = 0; k < 9; ++k) r[k] = t.rowmf[j][k];
-      R.push_back(r);
-    }
-    factor(R, C);
-    em.line("{  // orbit of class " + std::to_string(o[0]) + " (" + std::to_string(n) + ")");
+  for (auto& pl : plans) {
+    const int n = (int)pl.members.size();
+    em.line("{  // orbit of class " + std::to_string(pl.members[0]) + " (" + std::to_string(n) + ")");
     std::vector<Val> v(n);
     for (int i = 0; i < n; ++i) {
       v[i].zero = false;
-      v[i].name = "f[" + std::to_string(o[i]) + "]";
+      v[i].name = "f[" + std::to_string(pl.members[i]) + "]";
     }
-    em.fwht(v);
-    for (int oo = 0; oo < n; ++oo)
+    for (auto& p : pl.bm) {
+      const Val x = v[p.first], y = v[p.second];
+      v[p.first] = em.addsub(x, y, false);
+      v[p.second] = em.addsub(x, y, true);
+    }
+    for (int o = 0; o < n; ++o)
       for (int k = 0; k < 9; ++k) {
-        if (C[oo][k] == 0 || v[oo].zero) continue;
-        const ld c = v[oo].neg ? -C[oo][k] : C[oo][k];
-        em.line("m[" + std::to_string(k) + "] = fmaf(" + v[oo].name + ", " + flit(c) + ", m[" + std::to_string(k) +
+        if (pl.Cm[o][k] == 0 || v[o].zero) continue;
+        const ld c = v[o].neg ? -pl.Cm[o][k] : pl.Cm[o][k];
+        em.line("m[" + std::to_string(k) + "] = fmaf(" + v[o].name + ", " + flit(c) + ", m[" + std::to_string(k) +
                 "]);");
       }
     em.line("}");
@@ -228,32 +318,30 @@ static std::string gen_struct(const char* sname, const RlbmTable& t) {
        "], float (&m)[9]) {\n" + em.out + "  }\n";
   // equilibrium, relaxation and stores, one orbit at a time
   em.out.clear();
-  for (auto& o : orb) {
-    const int n = (int)o.size();
-    std::vector<std::vector<ld>> R, C;
-    for (int j : o) {
-      std::vector<ld> r(RLBM_NB);
-      for (int k = 0; k < RLBM_NB; ++k) r[k] = t.rowf[j][k];
-      R.push_back(r);
-    }
-    factor(R, C);
-    em.line("{  // orbit of class " + std::to_string(o[0]) + " (" + std::to_string(n) + ")");
+  for (auto& pl : plans) {
+    const int n = (int)pl.members.size();
+    em.line("{  // orbit of class " + std::to_string(pl.members[0]) + " (" + std::to_string(n) + ")");
     std::vector<Val> g(n);
-    for (int oo = 0; oo < n; ++oo) {
+    for (int o = 0; o < n; ++o) {
       std::string e;
       for (int k = 0; k < RLBM_NB; ++k) {
-        if (C[oo][k] == 0) continue;
-        if (e.empty()) e = "nb[" + std::to_string(k) + "] * " + flit(C[oo][k]);
-        else e = "fmaf(nb[" + std::to_string(k) + "], " + flit(C[oo][k]) + ", " + e + ")";
+        if (pl.Ce[o][k] == 0) continue;
+        if (e.empty()) e = "nb[" + std::to_string(k) + "] * " + flit(pl.Ce[o][k]);
+        else e = "fmaf(nb[" + std::to_string(k) + "], " + flit(pl.Ce[o][k]) + ", " + e + ")";
       }
       if (e.empty()) continue;
-      g[oo].zero = false;
-      g[oo].name = em.fresh("g");
-      em.line("const float " + g[oo].name + " = " + e + ";");
+      g[o].zero = false;
+      g[o].name = em.fresh("g");
+      em.line("const float " + g[o].name + " = " + e + ";");
     }
-    em.fwht(g);
+    for (int i = (int)pl.be.size() - 1; i >= 0; --i) {
+      const int x = pl.be[i].first, y = pl.be[i].second;
+      const Val a = g[x], b = g[y];
+      g[x] = em.addsub(a, b, false);
+      g[y] = em.addsub(a, b, true);
+    }
     for (int i = 0; i < n; ++i) {
-      const int j = o[i];
+      const int j = pl.members[i];
       std::string feq = g[i].zero ? "0.0f" : (g[i].neg ? "(-" + g[i].name + ")" : g[i].name);
       std::string om = "W0";
       if (t.ny[j] != 0) om = "fmaf(WY, " + flit((ld)t.ny[j]) + ", " + om + ")";

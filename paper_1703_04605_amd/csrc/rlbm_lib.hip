@@ -30,6 +30,9 @@
 namespace rlbm {
 
 constexpr int kBlock = 256;
+// Step kernel workgroups are single waves: a finished wave frees its slot for
+// the next tile at once instead of waiting for the rest of its workgroup.
+constexpr int kStepBlock = 64;
 constexpr int kWave = 64;
 // fourth word of a raw buffer descriptor on CDNA: 32-bit data format, no
 // swizzle, untyped loads and stores address bytes
@@ -361,7 +364,7 @@ struct TileStore {
 // for all of them).  In the FP16 mode the rows carry the per-class scale, so
 // the kernel relaxes the stored ratios h_j = (f_j - f^ref_j) / f^ref_j directly.
 template <int QN, int QMIN, int P, bool G, class Fx = void>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(step_waves(QN, P, G))))
+__global__ void __launch_bounds__(kStepBlock) __attribute__((amdgpu_waves_per_eu(step_waves(QN, P, G))))
 k_step(RlbmStepArgs a) {
   constexpr bool kFixed = !std::is_same<Fx, void>::value;
   using S = typename Traits<P>::S;
@@ -370,7 +373,7 @@ k_step(RlbmStepArgs a) {
   const TabPtr tb = as_tab(a.tab);
   const RlbmLayout& L = a.L;
   const int lane = (int)threadIdx.x & (kWave - 1);
-  const int t = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (kBlock / kWave) +
+  const int t = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (kStepBlock / kWave) +
                 __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   if (t >= a.ntiles) return;  // whole wave
   const int Q = tb->c.Q;
@@ -873,14 +876,14 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   if (!fn) return fail(c, RLBM_ESTATE, "no step kernel for this stencil");
   a.tiles_x = c->tiles_x;
   a.ntiles = c->ntiles;
-  const unsigned nwg = (unsigned)((c->ntiles + kBlock / kWave - 1) / (kBlock / kWave));
+  const unsigned nwg = (unsigned)((c->ntiles + kStepBlock / kWave - 1) / (kStepBlock / kWave));
   for (int i = 0; i < nsteps; ++i) {
     a.src = c->buf[c->cur];
     a.dst = c->buf[1 - c->cur];
     a.shift = c->shifted;
     a.offs = c->d_offs + (c->shifted ? RLBM_QMAX : 0);
     a.offs_st = c->d_offs;
-    hipLaunchKernelGGL(fn, dim3(nwg), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL(fn, dim3(nwg), dim3(kStepBlock), 0, s, a);
     HIPCHECK(c, hipGetLastError());
     c->cur ^= 1;
     c->shifted = 1;
