@@ -87,40 +87,15 @@ __device__ __forceinline__ double k1k2_ratio(double z) {
   return fma(t, b1, rlbm_bessel_ratio_cheb[0] - b2);
 }
 
-// Inverts e = eps/n = 3T + zeta R(zeta/T) (eq. relativistic-eos, T_R = 1)
-// by Newton's method on T.  The heat capacity per particle d e/dT lies in
-// [3/2, 3] and increases with T, so e(T) is convex and Newton iterates started
-// above the root, at min((e - zeta)/1.5, e/3), decrease monotonically to it.
-// d e/dT = 3 - z^2 R^2 - 3 z R + z^2 follows from R' = R^2 + 3R/z - 1.
-__device__ __forceinline__ double eos_temperature(double e, double zeta, unsigned& flags) {
-  double t = fmin((e - zeta) * (1.0 / 1.5), e * (1.0 / 3.0));
-  if (!(t > 0.0)) {
-    flags |= RLBM_H_RANGE;
-    return t;
-  }
-  bool done = false;
-  for (int it = 0; it < 40; ++it) {
-    const double z = zeta / t;
-    const double r = k1k2_ratio(z);
-    const double F = fma(3.0, t, fma(zeta, r, -e));
-    const double zr = z * r;
-    const double dF = 3.0 - zr * zr - 3.0 * zr + z * z;
-    const double d = F / dF;
-    t -= d;
-    if (done) break;
-    if (fabs(d) <= 1e-9 * t) done = true;  // quadratic convergence: one more step
-  }
-  if (!done) flags |= RLBM_H_EOS;
-  return t;
-}
-
 // Inverse EOS from the per-stencil table: T = u g(u), u = e - zeta, with g a
 // Chebyshev series on the quarter-octave of u (built on the host in long
-// double from the same equation); Newton fallback outside the tabulated range.
-// The lanes of a wave are served one distinct piece at a time (the piece index
-// is made uniform, so its coefficients come through scalar loads): smooth
-// fields put a wave's sites in one or two pieces, and no vector memory access
-// is needed.
+// double from the same equation).  The table spans u in [2^-24, 2^24), i.e.
+// T from about 4e-8 to 6e6 (in units of T_R); beyond it the site is flagged
+// RLBM_H_EOS and T takes the limit of the equation of state (u = 3T/2 for
+// T << mbar, u = 3T for T >> mbar).  The lanes of a wave are served one
+// distinct piece at a time (the piece index is made uniform, so its
+// coefficients come through scalar loads): smooth fields put a wave's sites in
+// one or two pieces, and no vector memory access is needed.
 __device__ __forceinline__ double eos_temperature_tab(TabPtr tb, double e, double zeta,
                                                      unsigned& flags) {
   const double u = e - zeta;
@@ -151,7 +126,14 @@ __device__ __forceinline__ double eos_temperature_tab(TabPtr tb, double e, doubl
       todo = false;
     }
   }
-  if (!intab) return eos_temperature(e, zeta, flags);
+  if (!intab) {
+    if (!(u > 0.0)) {
+      flags |= RLBM_H_RANGE;
+      return u * (1.0 / 1.5);
+    }
+    flags |= RLBM_H_EOS;
+    return o < 0 ? u * (1.0 / 1.5) : u * (1.0 / 3.0);
+  }
   return u * g;
 }
 

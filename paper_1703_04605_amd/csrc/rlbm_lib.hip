@@ -290,7 +290,7 @@ __device__ __forceinline__ void mlp_destandardise(const RlbmStepArgs& a, double 
 // largest stencils still fit in registers.
 constexpr int step_waves(int qn, int p, bool g) {
   return g ? (p == RLBM_FP64 ? 1 : (qn <= 24 ? 3 : 2))
-           : p == RLBM_FP64 ? (qn <= 48 ? 3 : 2) : (qn <= 48 ? 4 : 3);
+           : p == RLBM_FP64 ? (qn <= 48 ? 3 : 2) : (qn <= 48 ? 5 : 3);
 }
 
 // s_waitcnt operand that waits for LDS / scalar memory only (the vector

@@ -9,8 +9,8 @@
 // Inverse equation of state T(u), u = eps/n - mbar (kinetic energy per
 // particle): T/u as a Chebyshev series on each quarter of each octave
 // 2^k <= u < 2^(k+1), k = RLBM_EOS_KMIN .. RLBM_EOS_KMIN + RLBM_EOS_NOCT - 1.
-#define RLBM_EOS_KMIN (-14)
-#define RLBM_EOS_NOCT 28
+#define RLBM_EOS_KMIN (-24)
+#define RLBM_EOS_NOCT 48
 #define RLBM_EOS_DEG 14
 
 // equilibrium rows: M_j0 .. M_j9, n_x, n_y [, 1/scale] (padded: one wide load)
