@@ -232,9 +232,10 @@ def main():
                           "landau_iter_mean": h2["iter_sum"] / (sites * args.steps),
                           "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"],
                           "kernel": s2.step_kernel()}
-            # the same step kernel without the guess (the guided kernel is the
-            # table-driven one), and the fastest unguided path of this method
-            s3, ms3, _, h3 = time_path(st, fields, "fp32", args.steps, args.warmup, landau=landau, variant="table")
+            # the same step kernel (fixed-stencil or table-driven, whichever the
+            # guided run used) without the guess, and the fastest unguided path
+            same = "auto" if paths[key]["kernel"] == "fixed" else "table"
+            s3, ms3, _, h3 = time_path(st, fields, "fp32", args.steps, args.warmup, landau=landau, variant=same)
             m3 = sites * args.steps / (ms3 * 1e-3) / 1e6
             o3 = {k: v.cpu().numpy() for k, v in s3.moments().items()}
             del s3

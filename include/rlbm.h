@@ -219,8 +219,9 @@ long long rlbm_step_count(const rlbm_ctx* ctx);
  * in float32 and float16 storage, a kernel compiled with those rows as
  * constants and the class loops factored by the square's symmetry (built by
  * gen_fixed_stencils.cpp from the library's own table builder; used only when
- * the context's table matches bit for bit).  Both compute the same
- * arithmetic up to rounding order.
+ * the context's table matches bit for bit; for float32 storage also with
+ * the learned Landau guess).  Both compute the same arithmetic up to
+ * rounding order.
  * rlbm_set_step_variant: RLBM_STEP_AUTO (default: the fixed-stencil kernel
  * when one matches) or RLBM_STEP_TABLE (always the table-driven kernel);
  * RLBM_EINVAL on other values.  rlbm_step_kernel: which kernel the next

@@ -159,70 +159,64 @@ __device__ __forceinline__ void store_ghosts(S* __restrict__ q, const RlbmLayout
 
 // ------------------------------------------------------------------ learned guess
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f8 __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-__device__ __forceinline__ unsigned short to_bf16(float x) {
-  const unsigned u = __float_as_uint(x);
-  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+// x sigma(x), sigma(x) = 1 / (1 + 2^(-x log2 e)); exp2 overflows to inf for
+// x below about -88, which gives the limit -0.
+__device__ __forceinline__ float silu_f(float z) {
+  return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * -1.4426950408889634f));
 }
 
-__device__ __forceinline__ v4s pack4(float a, float b, float c, float d) {
-  v4s r;
-  r[0] = (short)to_bf16(a);
-  r[1] = (short)to_bf16(b);
-  r[2] = (short)to_bf16(c);
-  r[3] = (short)to_bf16(d);
-  return r;
-}
-
-__device__ __forceinline__ float silu_f(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
+// eight floats to bf16 (round to nearest even, four packed conversions)
+__device__ __forceinline__ bf8 to_bf8(const f8& v) { return __builtin_convertvector(v, bf8); }
 
 // The network evaluated for the 64 sites of a wave on the matrix cores
-// (32x32x8 bf16 products, float32 accumulation).  Each layer computes
+// (32x32x16 bf16 products, float32 accumulation).  Each layer computes
 // H^T = W A^T, with units along M and sites along N (two tiles of 32 sites);
 // lane l then holds units 8 (r/4) + 4 (l/32) + r%4 of site l%32 in
-// accumulator register r, which is exactly the B operand layout of the next
-// layer, so activations never leave their lanes.  Returns, in every lane, the
-// standardised outputs of the lane's own site.  All 64 lanes must be active.
+// accumulator register r.  Registers 0..7 and 8..15 of each output tile are
+// used as they are as the B operands of two k-steps of the next layer (the
+// weights are packed in the same unit order), so activations never leave
+// their lanes.  Returns, in every lane, the standardised outputs of the
+// lane's own site.  All 64 lanes must be active.
 __device__ __forceinline__ void mlp_wave(const RlbmStepArgs& a, const float xin[9], float out[3]) {
   const int l = threadIdx.x & 63;
   const int half = l >> 5;
   // The weight pointers pass through an empty asm statement so that the
-  // fragment loads stay at their use in every tile of the persistent loop
-  // instead of being hoisted out of it (which would keep all fragments live).
+  // fragment loads stay at their use instead of being hoisted (which would
+  // keep all fragments live).
   const unsigned short* fp = a.mlp_frag;
   const float* bp = a.mlp_bias;
   asm volatile("" : "+s"(fp), "+s"(bp));
-  const v4s* __restrict__ frag = (const v4s*)fp;
+  const bf8* __restrict__ frag = (const bf8*)fp;
   const v16f* __restrict__ bias = (const v16f*)bp;
 
-  // layer-1 B operands: inputs 8s + 4 half + i of site (l % 32) + 32 t
-  v4s bop[2][8];
+  // layer-1 B operands (one k-step): inputs 8 half + e of site (l % 32) + 32 t
+  bf8 bop[2][4];
+  {
+    f8 own, oth;
 #pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    float own[4], oth[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int ko = 8 * s + 4 * half + i, kt = 8 * s + 4 * (1 - half) + i;
-      own[i] = ko < 9 ? xin[ko] : 0.0f;
-      oth[i] = kt < 9 ? xin[kt] : 0.0f;
+    for (int e = 0; e < 8; ++e) {
+      const int ko = 8 * half + e, kt = 8 * (1 - half) + e;
+      own[e] = ko < 9 ? xin[ko] : 0.0f;
+      oth[e] = kt < 9 ? xin[kt] : 0.0f;
     }
-    float sw[4];
+    f8 sw;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sw[i] = __shfl_xor(oth[i], 32);
+    for (int e = 0; e < 8; ++e) sw[e] = __shfl_xor(oth[e], 32);
     // tile t = half: own site; tile 1 - half: the partner lane's site
-    const v4s pown = pack4(own[0], own[1], own[2], own[3]);
-    const v4s psw = pack4(sw[0], sw[1], sw[2], sw[3]);
-    bop[half ? 1 : 0][s] = pown;
-    bop[half ? 0 : 1][s] = psw;
+    const bf8 pown = to_bf8(own), psw = to_bf8(sw);
+    bop[half ? 1 : 0][0] = pown;
+    bop[half ? 0 : 1][0] = psw;
   }
 
   // hidden layers
-  int ksteps = 2;
+  int ksteps = 1;
 #pragma unroll
   for (int L = 0; L < 3; ++L) {
-    v4s nxt[2][8];
+    bf8 nxt[2][4];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
       const v16f b0 = bias[(RLBM_MLP_BFOFF[L] + m) * 64 + l];
@@ -230,22 +224,25 @@ __device__ __forceinline__ void mlp_wave(const RlbmStepArgs& a, const float xin[
       for (int t = 0; t < 2; ++t) {
         v16f acc = b0;
 #pragma unroll
-        for (int s = 0; s < 8; ++s)
+        for (int s = 0; s < 4; ++s)
           if (s < ksteps)
-            acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(frag[(RLBM_MLP_FOFF[L] + m * RLBM_MLP_KSTEPS[L] + s) * 64 + l],
-                                                           bop[t][s], acc, 0, 0, 0);
-        // registers 4q..4q+3 of tile m are the k-step 4m + q operand of the next layer
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag[(RLBM_MLP_FOFF[L] + m * RLBM_MLP_KSTEPS[L] + s) * 64 + l],
+                                                          bop[t][s], acc, 0, 0, 0);
+        f8 lo, hi;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          nxt[t][4 * m + q] = pack4(silu_f(acc[4 * q]), silu_f(acc[4 * q + 1]), silu_f(acc[4 * q + 2]),
-                                    silu_f(acc[4 * q + 3]));
+        for (int e = 0; e < 8; ++e) {
+          lo[e] = silu_f(acc[e]);
+          hi[e] = silu_f(acc[8 + e]);
+        }
+        nxt[t][2 * m] = to_bf8(lo);
+        nxt[t][2 * m + 1] = to_bf8(hi);
       }
     }
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int s = 0; s < 8; ++s) bop[t][s] = nxt[t][s];
-    ksteps = 8;
+      for (int s = 0; s < 4; ++s) bop[t][s] = nxt[t][s];
+    ksteps = 4;
   }
 
   // output layer: one tile of 32 rows (3 used)
@@ -255,8 +252,8 @@ __device__ __forceinline__ void mlp_wave(const RlbmStepArgs& a, const float xin[
   for (int t = 0; t < 2; ++t) {
     v16f acc = b3;
 #pragma unroll
-    for (int s = 0; s < 8; ++s)
-      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(frag[(RLBM_MLP_FOFF[3] + s) * 64 + l], bop[t][s], acc, 0, 0, 0);
+    for (int s = 0; s < 4; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag[(RLBM_MLP_FOFF[3] + s) * 64 + l], bop[t][s], acc, 0, 0, 0);
     res[t][0] = acc[0];
     res[t][1] = acc[1];
     res[t][2] = acc[2];
@@ -289,7 +286,7 @@ __device__ __forceinline__ void mlp_destandardise(const RlbmStepArgs& a, double 
 // wave's arithmetic with other waves' loads, while the class values of the
 // largest stencils still fit in registers.
 constexpr int step_waves(int qn, int p, bool g) {
-  return g ? (p == RLBM_FP64 ? 1 : (qn <= 24 ? 3 : 2))
+  return g ? (p == RLBM_FP64 ? 1 : (qn <= 44 ? 3 : 2))
            : p == RLBM_FP64 ? (qn <= 48 ? 3 : 2) : (qn <= 48 ? 5 : 3);
 }
 
@@ -584,12 +581,23 @@ StepFn step_kernel(int Q) {
   return k_step<160, 81, P, G>;
 }
 
-// Generated fixed-stencil kernels, by id (see rlbm_fixed_stencils.h).
-StepFn fixed_step(int id) {
+// Generated fixed-stencil kernels, by id (see rlbm_fixed_stencils.h); with
+// the learned guess for float32 storage only (nullptr otherwise).
+template <class ST, int PREC>
+StepFn fixed_kernel(bool guess) {
+  if constexpr (PREC == RLBM_FP32_DEV) {
+    if (guess) return k_step<ST::Q, ST::Q, PREC, true, ST>;
+  } else {
+    if (guess) return nullptr;
+  }
+  return k_step<ST::Q, ST::Q, PREC, false, ST>;
+}
+
+StepFn fixed_step(int id, bool guess) {
   switch (id) {
 #define RLBM_FIXED_CASE(ID, ST, PREC) \
   case ID:                            \
-    return k_step<rlbm_fixed::ST::Q, rlbm_fixed::ST::Q, PREC, false, rlbm_fixed::ST>;
+    return fixed_kernel<rlbm_fixed::ST, PREC>(guess);
     RLBM_FIXED_KERNELS(RLBM_FIXED_CASE)
 #undef RLBM_FIXED_CASE
     default:
@@ -871,8 +879,8 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
     for (int i = 0; i < 24; ++i) a.mlp_norm[i] = c->guess->h_norm[i];
     for (int i = 0; i < 9; ++i) a.mlp_norm[9 + i] = 1.0f / c->guess->h_norm[9 + i];
   }
-  StepFn fn = (!g && c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? fixed_step(c->fixed_id)
-                                                                       : select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
+  StepFn fn = (c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? fixed_step(c->fixed_id, g) : nullptr;
+  if (!fn) fn = select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
   if (!fn) return fail(c, RLBM_ESTATE, "no step kernel for this stencil");
   a.tiles_x = c->tiles_x;
   a.ntiles = c->ntiles;
@@ -955,7 +963,8 @@ extern "C" int rlbm_set_step_variant(rlbm_ctx* c, int variant) {
 extern "C" int rlbm_step_kernel(const rlbm_ctx* c) {
   if (!c) return RLBM_EINVAL;
   const bool g = c->guess != nullptr && c->h_tab->c.precision == RLBM_FP32_DEV;
-  return (!g && c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? RLBM_STEP_FIXED : RLBM_STEP_TABLE;
+  return (c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0 && fixed_step(c->fixed_id, g)) ? RLBM_STEP_FIXED
+                                                                                          : RLBM_STEP_TABLE;
 }
 
 extern "C" int rlbm_save_state(rlbm_ctx* c, void* dst, size_t bytes, long long* step, int* layout_flag,

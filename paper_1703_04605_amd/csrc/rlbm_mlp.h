@@ -11,12 +11,12 @@ constexpr int RLBM_MLP_IN[4] = {9, 64, 64, 64};
 constexpr int RLBM_MLP_OUT[4] = {64, 64, 64, 3};
 constexpr int RLBM_MLP_WOFF[4] = {0, 640, 4800, 8960};
 constexpr int RLBM_MLP_BOFF[4] = {576, 4736, 8896, 9152};
-// matrix-core fragments (32x32x8 bf16): output tiles of 32 units and k-steps of 8
+// matrix-core fragments (32x32x16 bf16): output tiles of 32 units and k-steps of 16
 constexpr int RLBM_MLP_TILES[4] = {2, 2, 2, 1};
-constexpr int RLBM_MLP_KSTEPS[4] = {2, 8, 8, 8};
-constexpr int RLBM_MLP_FOFF[4] = {0, 4, 20, 36};   // in (tile, kstep) items of 64 lanes x 4 bf16
+constexpr int RLBM_MLP_KSTEPS[4] = {1, 4, 4, 4};
+constexpr int RLBM_MLP_FOFF[4] = {0, 2, 10, 18};   // in (tile, kstep) items of 64 lanes x 8 bf16
 constexpr int RLBM_MLP_BFOFF[4] = {0, 2, 4, 6};    // in tiles of 64 lanes x 16 floats
-#define RLBM_MLP_NFRAG 44
+#define RLBM_MLP_NFRAG 22
 #define RLBM_MLP_NBFRAG 7
 
 struct rlbm_mlp {

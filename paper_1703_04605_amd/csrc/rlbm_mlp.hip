@@ -129,12 +129,19 @@ __global__ void k_output(const float* __restrict__ out, const float* __restrict_
   pred[b * 3 + 2] = out[b * 3 + 2] * norm[23] + norm[20];
 }
 
-// Fragments of the 32x32x8 bf16 matrix product for the in-step inference:
-// for output tile m, k-step s and lane l, the four values
-// W[32 m + l % 32][8 s + 4 (l / 32) + i], i = 0..3 (zero outside W).
+// Fragments of the 32x32x16 bf16 matrix product for the in-step inference:
+// for output tile m, k-step s and lane l (half h = l / 32), the eight values
+// W[32 m + l % 32][c(e)], e = 0..7, zero outside W.  The first layer takes its
+// inputs in natural order, c = 8 h + e.  The hidden and output layers take
+// them in the order in which the previous layer's accumulators hold them:
+// register r of output tile m' carries unit 32 m' + 8 (r / 4) + 4 h + r % 4,
+// so k-step s is made of registers 8 (s % 2) .. 8 (s % 2) + 7 of tile s / 2
+// and c = 16 s + 8 (e / 4) + 4 h + e % 4.  The product sums over k, so any
+// order shared by both operands gives the same result.
 __global__ void k_pack(const float* __restrict__ master, unsigned short* __restrict__ frag,
                        float* __restrict__ biasfrag) {
   const int l = threadIdx.x;  // 64 lanes, one block per (layer, tile, kstep) item
+  const int h = l >> 5;
   int item = blockIdx.x;
   for (int L = 0; L < 4; ++L) {
     const int nin = RLBM_MLP_IN[L], nout = RLBM_MLP_OUT[L];
@@ -144,11 +151,11 @@ __global__ void k_pack(const float* __restrict__ master, unsigned short* __restr
       const int m = item / ks, s = item - m * ks;
       const float* W = master + RLBM_MLP_WOFF[L];
       const int row = 32 * m + (l & 31);
-      for (int i = 0; i < 4; ++i) {
-        const int col = 8 * s + 4 * (l >> 5) + i;
+      for (int e = 0; e < 8; ++e) {
+        const int col = L == 0 ? 8 * h + e : 16 * s + 8 * (e >> 2) + 4 * h + (e & 3);
         const float w = (row < nout && col < nin) ? W[row * nin + col] : 0.0f;
         const unsigned u = __float_as_uint(w);
-        frag[((size_t)(RLBM_MLP_FOFF[L] + item) * 64 + l) * 4 + i] =
+        frag[((size_t)(RLBM_MLP_FOFF[L] + item) * 64 + l) * 8 + e] =
             (unsigned short)(((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16) & 0xFFFFu);
       }
       if (s == 0) {
@@ -215,7 +222,7 @@ extern "C" int rlbm_mlp_create(rlbm_mlp** out, const float* params, const float*
     m->A[L] = p; p += act;
   }
   m->loss = p; p += 1;
-  if (hipMalloc((void**)&m->frag, sizeof(unsigned short) * 4 * RLBM_MLP_NFRAG * 64) != hipSuccess ||
+  if (hipMalloc((void**)&m->frag, sizeof(unsigned short) * 8 * RLBM_MLP_NFRAG * 64) != hipSuccess ||
       hipMalloc((void**)&m->biasfrag, sizeof(float) * 16 * RLBM_MLP_NBFRAG * 64) != hipSuccess ||
       hipMalloc((void**)&m->Z4, sizeof(float) * 3 * (size_t)max_batch) != hipSuccess ||
       hipMalloc((void**)&m->D[0], sizeof(float) * 3 * act) != hipSuccess) {

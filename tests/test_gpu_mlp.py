@@ -108,12 +108,12 @@ def test_in_step_inference_matches_oracle():
     assert (err < 2e-2).all(), err
 
 
-@pytest.mark.parametrize("landau", ["newton", "fixed_point"])
-def test_guided_step_matches_plain_and_saves_iterations(landau):
+@pytest.mark.parametrize("landau,variant", [("newton", "table"), ("fixed_point", "table"), ("newton", "auto")])
+def test_guided_step_matches_plain_and_saves_iterations(landau, variant):
     """With a trained network the fields equal the unguided run's to 1e-6 and
-    the Landau solve takes fewer iterations.  Both runs use the table-driven
-    step kernel (the guided kernel is built on it), so the comparison sees the
-    guess's effect only, not the rounding order of the fixed-stencil kernel."""
+    the Landau solve takes fewer iterations.  Both runs use the same step
+    kernel (table-driven, or both the generated fixed-stencil kernel), so the
+    comparison sees the guess's effect only, not a change of rounding order."""
     from paper_1703_04605_amd import rlbm, learned_guess
     from tests.helpers import field_errors
     raw9, target = moment_batch(8192, seed=4)
@@ -127,10 +127,10 @@ def test_guided_step_matches_plain_and_saves_iterations(landau):
     for guided in (False, True):
         s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], precision="fp32")
         s.init_fields(*fields, tau=0.9, landau=landau)
-        s.set_step_variant("table")
+        s.set_step_variant(variant)
         if guided:
             s.set_landau_guess(net)
-        assert s.step_kernel() == "table"
+        assert s.step_kernel() == ("table" if variant == "table" else "fixed")
         s.step(30)
         h = s.health()
         res[guided] = ({k: v.cpu().numpy() for k, v in s.moments().items()}, h["iter_sum"] / (128 * 128 * 30))
