@@ -105,6 +105,13 @@ struct Emitter {
   }
 };
 
+// double literal that reads back to the same value
+static std::string dlit(double x) {
+  char buf[64];
+  snprintf(buf, sizeof buf, "%.17e", x);
+  return buf;
+}
+
 static std::string flit(ld x) {
   char b[64];
   snprintf(b, sizeof b, "%.9ef", (double)(float)x);
@@ -290,6 +297,14 @@ static std::string gen_struct(const char* sname, const RlbmTable& t) {
   s += "struct " + std::string(sname) + " {\n";
   s += "  static constexpr int Q = " + std::to_string(Q) + ";\n";
   s += "  static constexpr int orbits = " + std::to_string(plans.size()) + ";\n";
+  // class displacements (lattice units), indexed by template constants only
+  std::string sx = "  static constexpr int kNx[" + std::to_string(Q) + "] = {";
+  std::string sy = "  static constexpr int kNy[" + std::to_string(Q) + "] = {";
+  for (int j = 0; j < Q; ++j) {
+    sx += (j ? ", " : "") + std::to_string(t.nx[j]);
+    sy += (j ? ", " : "") + std::to_string(t.ny[j]);
+  }
+  s += sx + "};\n" + sy + "};\n";
   // moments
   em.out.clear();
   for (auto& pl : plans) {
@@ -354,6 +369,23 @@ static std::string gen_struct(const char* sname, const RlbmTable& t) {
   }
   s += "  template <class Store>\n  static __device__ __forceinline__ void collide(float (&f)[" + std::to_string(Q) +
        "], const float (&nb)[RLBM_NB], float W0, float WX, float WY, Store& st) {\n" + em.out + "  }\n";
+  // the stencil's float64 constants (Appendix A at mbar, deviation reference)
+  const RlbmConsts& c = t.c;
+  s += "  struct C {\n";
+  const std::pair<const char*, double> sc[] = {{"zeta", c.zeta}, {"inv_zeta", c.inv_zeta}, {"v0", c.v0},
+                                                {"a1", c.a1},     {"invA", c.invA},         {"invB", c.invB},
+                                                {"c1", c.c1},     {"c0", c.c0},             {"inv_s3C", c.inv_s3C},
+                                                {"d0", c.d0},     {"invD", c.invD},         {"invE", c.invE}};
+  for (auto& kv : sc) s += "    static constexpr double " + std::string(kv.first) + " = " + dlit(kv.second) + ";\n";
+  auto table_fn = [&s](const char* name, const double* v, int n) {
+    s += "    static __device__ __forceinline__ constexpr double " + std::string(name) + "(int k) {\n";
+    s += "      switch (k) {\n";
+    for (int k = 0; k < n; ++k) s += "        case " + std::to_string(k) + ": return " + dlit(v[k]) + ";\n";
+    s += "      }\n      return 0.0;\n    }\n";
+  };
+  table_fn("ref_mom", c.ref_mom, 9);
+  table_fn("nb_ref", c.nb_ref, RLBM_NB);
+  s += "  };\n";
   s += "};\n";
   return s;
 }

@@ -211,9 +211,18 @@ __device__ __forceinline__ int landau_solve(double T00, double T0x, double T0y, 
 // distribution on the 10 in-plane second-order polynomials (Appendix B; T_R = 1
 // so a_k = b_k).  From the moments int f p = U, int f p p = q U U - T eta,
 // q = mbar K_3(z)/K_2(z) = zeta R + 4T, int f = R/zeta.
-__device__ __forceinline__ void projections(TabPtr tb, double T, double R, double U0, double Ux, double Uy,
-                                            double b[RLBM_NB]) {
+// Appendix A constants at mbar (T_R = 1) used by the projections.
+struct ProjConsts {
+  double zeta, inv_zeta, a1, invA, invB, c1, c0, inv_s3C, d0, invD, invE;
+};
+
+__device__ __forceinline__ ProjConsts proj_consts(TabPtr tb) {
   const auto& c = tb->c;
+  return ProjConsts{c.zeta, c.inv_zeta, c.a1, c.invA, c.invB, c.c1, c.c0, c.inv_s3C, c.d0, c.invD, c.invE};
+}
+
+__device__ __forceinline__ void projections(const ProjConsts& c, double T, double R, double U0, double Ux,
+                                            double Uy, double b[RLBM_NB]) {
   const double b0 = R * c.inv_zeta;
   const double q = fma(c.zeta, R, 4.0 * T);
   b[0] = b0;
@@ -227,6 +236,11 @@ __device__ __forceinline__ void projections(TabPtr tb, double T, double R, doubl
   b[7] = q * Uy * Uy * (0.5 * c.invE);
   b[8] = q * (Uy * Uy - 2.0 * Ux * Ux) * (0.28867513459481288225 * c.invE);  // 1/(2 sqrt 3)
   b[9] = q * Ux * Uy * c.invE;
+}
+
+__device__ __forceinline__ void projections(TabPtr tb, double T, double R, double U0, double Ux, double Uy,
+                                            double b[RLBM_NB]) {
+  projections(proj_consts(tb), T, R, U0, Ux, Uy, b);
 }
 
 // Relaxation time per site from eta/s (Sec. IV): tau = 1/2 + (3/2)(eta/s) s hbar_c v0/(P dx)

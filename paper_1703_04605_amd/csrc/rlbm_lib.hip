@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <utility>
 #include <cmath>
 #include <vector>
 
@@ -95,10 +96,12 @@ __device__ __forceinline__ double newton_thresh(double tol) { return 0.1 * sqrt(
 
 // guess (eps0, ux0, uy0): starting point of the Landau solve; eps0 <= 0 means
 // none (Newton from T^00, fixed point from u = 0)
-__device__ __forceinline__ Macro macroscopic(TabPtr tb, double N0, double Nx, double Ny,
-                                             double T00, double T0x, double T0y, double Txx, double Txy,
-                                             double Tyy, double tol, int maxit, int method, double eps0 = 0.0,
-                                             double ux0 = 0.0, double uy0 = 0.0) {
+// (zeta = mbar and its inverse passed in, so that kernels with the stencil's
+// constants compiled in need no table read for them)
+__device__ __forceinline__ Macro macroscopic_z(TabPtr tb, double zeta, double inv_zeta, double N0, double Nx,
+                                               double Ny, double T00, double T0x, double T0y, double Txx,
+                                               double Txy, double Tyy, double tol, int maxit, int method,
+                                               double eps0, double ux0, double uy0) {
   Macro m;
   m.flags = 0;
   const bool guess = eps0 > 0.0 && eps0 < T00 && ux0 * ux0 + uy0 * uy0 < 1.0;
@@ -115,15 +118,47 @@ __device__ __forceinline__ Macro macroscopic(TabPtr tb, double N0, double Nx, do
   m.gamma = rsqrt_nr(1.0 - u2);
   m.n = m.gamma * (N0 - m.ux * Nx - m.uy * Ny);
   if (!(m.n > 0.0) || !(m.eps > 0.0)) m.flags |= RLBM_H_RANGE;
-  const double zeta = tb->c.zeta;
   const double e = div_nr(m.eps, m.n);
   m.T = eos_temperature_tab(tb, e, zeta, m.flags);
   m.P = m.n * m.T;
   // K1/K2 at z = zeta/T from the EOS itself: zeta R = e - 3T
-  m.R = (e - 3.0 * m.T) * tb->c.inv_zeta;
+  m.R = (e - 3.0 * m.T) * inv_zeta;
   if (!isfinite(m.T) || !isfinite(m.eps) || !isfinite(m.n) || !isfinite(m.R)) m.flags |= RLBM_H_NAN;
   return m;
 }
+
+__device__ __forceinline__ Macro macroscopic(TabPtr tb, double N0, double Nx, double Ny,
+                                             double T00, double T0x, double T0y, double Txx, double Txy,
+                                             double Tyy, double tol, int maxit, int method, double eps0 = 0.0,
+                                             double ux0 = 0.0, double uy0 = 0.0) {
+  return macroscopic_z(tb, tb->c.zeta, tb->c.inv_zeta, N0, Nx, Ny, T00, T0x, T0y, Txx, Txy, Tyy, tol, maxit,
+                       method, eps0, ux0, uy0);
+}
+
+// Per-stencil constants of the step: from the table, or compiled in for the
+// generated stencils (struct C of rlbm_fixed_stencils.h, same values).
+template <class Fx>
+struct StepConsts {
+  static __device__ __forceinline__ double zeta(TabPtr) { return Fx::C::zeta; }
+  static __device__ __forceinline__ double inv_zeta(TabPtr) { return Fx::C::inv_zeta; }
+  static __device__ __forceinline__ double v0(TabPtr) { return Fx::C::v0; }
+  static __device__ __forceinline__ double ref_mom(TabPtr, int k) { return Fx::C::ref_mom(k); }
+  static __device__ __forceinline__ double nb_ref(TabPtr, int k) { return Fx::C::nb_ref(k); }
+  static __device__ __forceinline__ ProjConsts proj(TabPtr) {
+    using C = typename Fx::C;
+    return ProjConsts{C::zeta, C::inv_zeta, C::a1, C::invA, C::invB, C::c1, C::c0, C::inv_s3C, C::d0, C::invD,
+                      C::invE};
+  }
+};
+template <>
+struct StepConsts<void> {
+  static __device__ __forceinline__ double zeta(TabPtr tb) { return tb->c.zeta; }
+  static __device__ __forceinline__ double inv_zeta(TabPtr tb) { return tb->c.inv_zeta; }
+  static __device__ __forceinline__ double v0(TabPtr tb) { return tb->c.v0; }
+  static __device__ __forceinline__ double ref_mom(TabPtr tb, int k) { return tb->c.ref_mom[k]; }
+  static __device__ __forceinline__ double nb_ref(TabPtr tb, int k) { return tb->c.nb_ref[k]; }
+  static __device__ __forceinline__ ProjConsts proj(TabPtr tb) { return proj_consts(tb); }
+};
 
 // ------------------------------------------------------------------ layout
 
@@ -163,8 +198,8 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f8 __attribute__((ext_vector_type(8)));
 typedef float v16f __attribute__((ext_vector_type(16)));
 
-// x sigma(x), sigma(x) = 1 / (1 + 2^(-x log2 e)); exp2 overflows to inf for
-// x below about -88, which gives the limit -0.
+// SiLU(z) = z / (1 + 2^(-z log2 e)); exp2 overflows to inf for z below
+// about -88, which gives the limit -0.
 __device__ __forceinline__ float silu_f(float z) {
   return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(z * -1.4426950408889634f));
 }
@@ -190,18 +225,22 @@ __device__ __forceinline__ void mlp_wave(const RlbmStepArgs& a, const float xin[
   const unsigned short* fp = a.mlp_frag;
   const float* bp = a.mlp_bias;
   asm volatile("" : "+s"(fp), "+s"(bp));
-  const bf8* __restrict__ frag = (const bf8*)fp;
-  const v16f* __restrict__ bias = (const v16f*)bp;
+  const bf8* __restrict__ fr = (const bf8*)fp;
+  const v16f* __restrict__ br = (const v16f*)bp;
+  auto frag = [&](int item) { return fr[item * 64 + l]; };
+  auto bias = [&](int item) { return br[item * 64 + l]; };
 
   // layer-1 B operands (one k-step): inputs 8 half + e of site (l % 32) + 32 t
   bf8 bop[2][4];
   {
+    // inputs 0..7 for half 0; input 8 and zeros for half 1 (selects, not
+    // a lane-dependent register index)
     f8 own, oth;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-      const int ko = 8 * half + e, kt = 8 * (1 - half) + e;
-      own[e] = ko < 9 ? xin[ko] : 0.0f;
-      oth[e] = kt < 9 ? xin[kt] : 0.0f;
+      const float hi = e == 0 ? xin[8] : 0.0f;
+      own[e] = half ? hi : xin[e];
+      oth[e] = half ? xin[e] : hi;
     }
     f8 sw;
 #pragma unroll
@@ -219,14 +258,14 @@ __device__ __forceinline__ void mlp_wave(const RlbmStepArgs& a, const float xin[
     bf8 nxt[2][4];
 #pragma unroll
     for (int m = 0; m < 2; ++m) {
-      const v16f b0 = bias[(RLBM_MLP_BFOFF[L] + m) * 64 + l];
+      const v16f b0 = bias(RLBM_MLP_BFOFF[L] + m);
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
         v16f acc = b0;
 #pragma unroll
         for (int s = 0; s < 4; ++s)
           if (s < ksteps)
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag[(RLBM_MLP_FOFF[L] + m * RLBM_MLP_KSTEPS[L] + s) * 64 + l],
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag(RLBM_MLP_FOFF[L] + m * RLBM_MLP_KSTEPS[L] + s),
                                                           bop[t][s], acc, 0, 0, 0);
         f8 lo, hi;
 #pragma unroll
@@ -247,13 +286,13 @@ __device__ __forceinline__ void mlp_wave(const RlbmStepArgs& a, const float xin[
 
   // output layer: one tile of 32 rows (3 used)
   float res[2][3];
-  const v16f b3 = bias[RLBM_MLP_BFOFF[3] * 64 + l];
+  const v16f b3 = bias(RLBM_MLP_BFOFF[3]);
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     v16f acc = b3;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag[(RLBM_MLP_FOFF[3] + s) * 64 + l], bop[t][s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(frag(RLBM_MLP_FOFF[3] + s), bop[t][s], acc, 0, 0, 0);
     res[t][0] = acc[0];
     res[t][1] = acc[1];
     res[t][2] = acc[2];
@@ -333,15 +372,32 @@ template <int P>
 struct TileStore {
   __amdgpu_buffer_rsrc_t r;
   int vst;
-  const __attribute__((address_space(4))) unsigned* own;
+  unsigned ob, ocs;  // own storage of class J at byte offset ob + J ocs
   template <int J>
   __device__ __forceinline__ void put(float v) {
     if constexpr (P == RLBM_FP32_DEV)
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vst, own[J], 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vst, ob + J * ocs, 0);
     else
-      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, vst, own[J], 0);
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, vst, ob + J * ocs,
+                                            0);
   }
 };
+
+// Pulls of a generated stencil: offsets from the class displacements known at
+// compile time and three per-lattice scalars, so no offset table is read.
+template <class Fx, int P, class S, int... J>
+__device__ __forceinline__ void pull_fixed(S (&raw)[sizeof...(J)], __amdgpu_buffer_rsrc_t r, int vld,
+                                           const RlbmStepArgs& a, std::integer_sequence<int, J...>) {
+  auto one = [&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    const unsigned off = a.fo_base + j * a.fo_cs - Fx::kNy[j] * a.fo_rs - Fx::kNx[j] * a.fo_es;
+    if constexpr (P == RLBM_FP32_DEV)
+      raw[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vld, off, 0));
+    else
+      raw[j] = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, vld, off, 0));
+  };
+  (one(std::integral_constant<int, J>{}), ...);
+}
 
 // One time step for one tile per wave (kWave consecutive sites of a row), for
 // a stencil of QMIN..QN classes.  The class loops are fully unrolled, so the
@@ -364,6 +420,7 @@ template <int QN, int QMIN, int P, bool G, class Fx = void>
 __global__ void __launch_bounds__(kStepBlock) __attribute__((amdgpu_waves_per_eu(step_waves(QN, P, G))))
 k_step(RlbmStepArgs a) {
   constexpr bool kFixed = !std::is_same<Fx, void>::value;
+  using SC = StepConsts<Fx>;
   using S = typename Traits<P>::S;
   using A = typename Traits<P>::A;
   typedef const __attribute__((address_space(4))) unsigned* OffPtr;
@@ -393,6 +450,9 @@ k_step(RlbmStepArgs a) {
 
   // pull: f_j(x, t) = f*_j(x - n_j, t - 1) (exact streaming)
   S raw[QN];
+  if constexpr (kFixed) {
+    pull_fixed<Fx, P>(raw, rs_ld, vld, a, std::make_integer_sequence<int, QN>{});
+  } else {
 #pragma unroll
   for (int j = 0; j < QN; ++j) {
     if constexpr (P == RLBM_FP64)
@@ -401,6 +461,7 @@ k_step(RlbmStepArgs a) {
       raw[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs_ld, vld, pull[j], 0));
     else
       raw[j] = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs_ld, vld, pull[j], 0));
+  }
   }
 
   // moments (eq. mj-discrete-second-moment) as one multiply-add per
@@ -432,7 +493,7 @@ k_step(RlbmStepArgs a) {
   for (int k = 0; k < 9; ++k) asm volatile("" : "+v"(m[k]));
   double md[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) md[k] = (P == RLBM_FP64) ? (double)m[k] : tb->c.ref_mom[k] + (double)m[k];
+  for (int k = 0; k < 9; ++k) md[k] = (P == RLBM_FP64) ? (double)m[k] : SC::ref_mom(tb, k) + (double)m[k];
 
   double e0 = 0.0, ux0 = 0.0, uy0 = 0.0;
   if constexpr (G) {
@@ -441,22 +502,22 @@ k_step(RlbmStepArgs a) {
     mlp_wave(a, xin, yo);
     mlp_destandardise(a, md[0], yo, e0, ux0, uy0);
   }
-  Macro mac = macroscopic(tb, md[0], md[1], md[2], md[3], md[4], md[5], md[6], md[7], md[8], a.landau_tol,
-                          a.landau_maxit, a.landau_method, e0, ux0, uy0);
+  Macro mac = macroscopic_z(tb, SC::zeta(tb), SC::inv_zeta(tb), md[0], md[1], md[2], md[3], md[4], md[5], md[6],
+                            md[7], md[8], a.landau_tol, a.landau_maxit, a.landau_method, e0, ux0, uy0);
   const double tau = a.tau_mode == RLBM_TAU_CONST ? a.tau : tau_eta_over_s(a.tk1, a.tk2, mac.n, mac.T);
   double b[RLBM_NB];
-  projections(tb, mac.T, mac.R, mac.gamma, mac.gamma * mac.ux, mac.gamma * mac.uy, b);
+  projections(SC::proj(tb), mac.T, mac.R, mac.gamma, mac.gamma * mac.ux, mac.gamma * mac.uy, b);
   // Anderson-Witting frequency p_i.U/(p_i^0 tau) = gamma (1 - v0 n_i.u)/tau (eq. discrete-relativistic-boltzmann)
   const double w0 = a.tau_mode == RLBM_TAU_CONST ? mac.gamma * a.inv_tau : div_nr(mac.gamma, tau);
-  const double wx = -w0 * tb->c.v0 * mac.ux, wy = -w0 * tb->c.v0 * mac.uy;
+  const double wx = -w0 * SC::v0(tb) * mac.ux, wy = -w0 * SC::v0(tb) * mac.uy;
   A nb[RLBM_NB];
 #pragma unroll
-  for (int k = 0; k < RLBM_NB; ++k) nb[k] = (A)(mac.n * b[k] - (P == RLBM_FP64 ? 0.0 : tb->c.nb_ref[k]));
+  for (int k = 0; k < RLBM_NB; ++k) nb[k] = (A)(mac.n * b[k] - (P == RLBM_FP64 ? 0.0 : SC::nb_ref(tb, k)));
   const A W0 = (A)w0, WX = (A)wx, WY = (A)wy;
 
   // equilibrium (eq. mj-discrete-feq) and relaxation, stored at the own site
   if constexpr (kFixed) {
-    TileStore<P> st{rs_st, vst, own};
+    TileStore<P> st{rs_st, vst, a.fo_base, a.fo_cs};
     Fx::collide(f, nb, W0, WX, WY, st);
   } else {
     const auto* rows = Rows<P>::e(tb);
@@ -884,6 +945,10 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   if (!fn) return fail(c, RLBM_ESTATE, "no step kernel for this stencil");
   a.tiles_x = c->tiles_x;
   a.ntiles = c->ntiles;
+  // byte offsets as in the offset table (range-checked below 2^31 there)
+  const long long es = c->h_tab->c.precision == RLBM_FP64 ? 8 : c->h_tab->c.precision == RLBM_FP32_DEV ? 4 : 2;
+  a.fo_base = (unsigned)(es * ((long long)c->L.Sy * c->L.rs + c->L.Sx));
+  a.fo_cs = (unsigned)(es * c->L.cs);
   const unsigned nwg = (unsigned)((c->ntiles + kStepBlock / kWave - 1) / (kStepBlock / kWave));
   for (int i = 0; i < nsteps; ++i) {
     a.src = c->buf[c->cur];
@@ -891,6 +956,8 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
     a.shift = c->shifted;
     a.offs = c->d_offs + (c->shifted ? RLBM_QMAX : 0);
     a.offs_st = c->d_offs;
+    a.fo_rs = c->shifted ? (int)(es * c->L.rs) : 0;
+    a.fo_es = c->shifted ? (int)es : 0;
     hipLaunchKernelGGL(fn, dim3(nwg), dim3(kStepBlock), 0, s, a);
     HIPCHECK(c, hipGetLastError());
     c->cur ^= 1;

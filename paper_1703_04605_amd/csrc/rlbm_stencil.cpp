@@ -496,6 +496,12 @@ uint64_t rlbm_table_fingerprint(const RlbmTable* t) {
     mix(t->rowmf[j], sizeof(float) * 9);
     mix(t->rowf[j], sizeof(float) * RLBM_NB);
   }
+  // float64 constants compiled into the generated kernels
+  const RlbmConsts& c = t->c;
+  const double cs[] = {c.zeta, c.inv_zeta, c.v0, c.a1, c.invA, c.invB, c.c1, c.c0, c.inv_s3C, c.d0, c.invD, c.invE};
+  mix(cs, sizeof cs);
+  mix(c.ref_mom, sizeof c.ref_mom);
+  mix(c.nb_ref, sizeof c.nb_ref);
   return h;
 }
 

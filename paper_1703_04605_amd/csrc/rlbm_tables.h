@@ -108,6 +108,11 @@ struct RlbmStepArgs {
   // n_y rs + n_x when pulling), offs_st = own storage of f_j; QMAX entries each.
   const unsigned* offs;
   const unsigned* offs_st;
+  // The same offsets as arithmetic, for kernels that know n_j at compile
+  // time: own_j = fo_base + j fo_cs, source = own_j - n_y fo_rs - n_x fo_es
+  // (fo_rs = fo_es = 0 when reading in place).
+  unsigned fo_base, fo_cs;
+  int fo_rs, fo_es;
   int shift;           // 1: pull f_j(x - n_j) (post-collision state), 0: read f_j(x)
   int tiles_x;         // wave tiles (64 sites) per row
   int ntiles;          // wave tiles of the lattice
