@@ -46,7 +46,8 @@ def measured_traffic(precision, nx, ny):
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
-def time_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton", guess=None, variant="auto"):
+def time_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton", guess=None, variant="auto",
+              warm=False):
     import torch
     from paper_1703_04605_amd import rlbm
     s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=2, precision=precision)
@@ -54,6 +55,8 @@ def time_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton", gu
     s.set_step_variant(variant)
     if guess is not None:
         s.set_landau_guess(guess)
+    if warm:
+        s.set_warm_start(True)
     s.step(warmup)
     s.health(reset=True)
     stream = torch.cuda.current_stream()
@@ -163,6 +166,7 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the other precision paths")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-guess", action="store_true", help="skip the learned-guess paths")
+    ap.add_argument("--no-warm", action="store_true", help="skip the warm-start paths")
     ap.add_argument("--calibration-copy", action="store_true", help="also run a 256 MiB device copy")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-problem workload")
     args = ap.parse_args()
@@ -251,6 +255,32 @@ def main():
                 paths[key]["speedup_vs_fp64"] = m2 / paths["fp64"]["mlups"]
             del s2
         paths["guess_training_loss"] = {"first": l0, "last": l1}
+    if not args.no_warm and not args.no_compare:
+        # Landau solve started from each site's frame of the previous step,
+        # against the same kernel started plainly
+        for key, landau in (("fp32_warm", "newton"), ("fp32_warm_fixed_point", "fixed_point")):
+            s2, ms2, _, h2 = time_path(st, fields, "fp32", args.steps, args.warmup, landau=landau, warm=True)
+            m2 = sites * args.steps / (ms2 * 1e-3) / 1e6
+            ab = 2 * q * 4 * sites / (ms2 / args.steps * 1e-3) / 1e9
+            o2 = {k: v.cpu().numpy() for k, v in s2.moments().items()}
+            kern = s2.step_kernel()
+            del s2
+            s3, ms3, _, h3 = time_path(st, fields, "fp32", args.steps, args.warmup, landau=landau)
+            m3 = sites * args.steps / (ms3 * 1e-3) / 1e6
+            o3 = {k: v.cpu().numpy() for k, v in s3.moments().items()}
+            del s3
+            paths[key] = {"mlups": m2, "ms_per_step": ms2 / args.steps, "hbm_frac": ab / HBM_PEAK_GBS,
+                          "landau_iter_mean": h2["iter_sum"] / (sites * args.steps),
+                          "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"], "kernel": kern,
+                          "extra_bytes_per_site": 24,
+                          "plain_same_kernel_mlups": m3,
+                          "plain_landau_iter_mean": h3["iter_sum"] / (sites * args.steps),
+                          "speedup_vs_plain": m2 / m3,
+                          "max_rel_err_vs_plain": {k: float(np.abs(o2[k] - o3[k]).max() / np.abs(o3[k]).max())
+                                                   for k in ("n", "eps", "T", "P", "ux", "uy")}}
+            gkey = "fp32_guess" if landau == "newton" else "fp32_guess_fixed_point"
+            if gkey in paths:
+                paths[key]["speedup_vs_learned_guess"] = m2 / paths[gkey]["mlups"]
 
     if not args.no_batched and not args.no_compare:
         paths["batched_riemann_64x500"] = time_batched()

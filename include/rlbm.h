@@ -279,6 +279,19 @@ int rlbm_set_landau_guess(rlbm_ctx* ctx, const rlbm_mlp* m);
  * eps, u_x, u_y.  RLBM_ESTATE without fields or network. */
 int rlbm_landau_guess_fields(rlbm_ctx* ctx, float* out, void* stream);
 
+/* Warm start of the Landau-frame solve (Sec. II.A): makes every later
+ * rlbm_step of ctx start the solve at each site from the frame (eps, u_x,
+ * u_y) that the site converged to in the previous step, kept in a
+ * library-owned device buffer of 3 nx ny float32 values (allocated and
+ * cleared here, never inside rlbm_step; freed by rlbm_destroy).  The first
+ * step after enabling starts as without it.  The solve that follows is
+ * unchanged, so the fields agree with the plain path to the Landau
+ * tolerance.  enable = 0 turns it off (the buffer is kept for reuse); a
+ * later rlbm_init_fields turns it off too.  RLBM_ESTATE without fields,
+ * RLBM_EINVAL while a learned guess is set (the two are exclusive; so
+ * rlbm_set_landau_guess returns RLBM_EINVAL while the warm start is on). */
+int rlbm_set_warm_start(rlbm_ctx* ctx, int enable);
+
 /*
  * Batched 1D problems in one persistent launch.  Each problem is an Nx x 1
  * lattice with outflow ends, float32 deviation storage and tau from eta/s

@@ -496,14 +496,26 @@ k_step(RlbmStepArgs a) {
   for (int k = 0; k < 9; ++k) md[k] = (P == RLBM_FP64) ? (double)m[k] : SC::ref_mom(tb, k) + (double)m[k];
 
   double e0 = 0.0, ux0 = 0.0, uy0 = 0.0;
+  const long long wsite = (long long)y * L.nx + min(x, L.nx - 1);
   if constexpr (G) {
     float xin[9], yo[3];
     mlp_inputs(a, md, xin);
     mlp_wave(a, xin, yo);
     mlp_destandardise(a, md[0], yo, e0, ux0, uy0);
+  } else if (a.warm) {  // the frame this site converged to in the previous step
+    e0 = a.warm[wsite];
+    ux0 = a.warm[wsite + a.warm_plane];
+    uy0 = a.warm[wsite + 2 * a.warm_plane];
   }
   Macro mac = macroscopic_z(tb, SC::zeta(tb), SC::inv_zeta(tb), md[0], md[1], md[2], md[3], md[4], md[5], md[6],
                             md[7], md[8], a.landau_tol, a.landau_maxit, a.landau_method, e0, ux0, uy0);
+  if constexpr (!G) {
+    if (a.warm && active) {
+      a.warm[wsite] = (float)mac.eps;
+      a.warm[wsite + a.warm_plane] = (float)mac.ux;
+      a.warm[wsite + 2 * a.warm_plane] = (float)mac.uy;
+    }
+  }
   const double tau = a.tau_mode == RLBM_TAU_CONST ? a.tau : tau_eta_over_s(a.tk1, a.tk2, mac.n, mac.T);
   double b[RLBM_NB];
   projections(SC::proj(tb), mac.T, mac.R, mac.gamma, mac.gamma * mac.ux, mac.gamma * mac.uy, b);
@@ -738,6 +750,9 @@ struct rlbm_ctx {
   int nslots = 0;               // health slots: one per tile
   double tk1 = 0, tk2 = 0;
   const rlbm_mlp* guess = nullptr;
+  float* d_warm = nullptr;          // warm-start frames (3 planes of nx ny floats)
+  size_t warm_cap = 0;              // floats allocated at d_warm
+  bool warm = false;
   int fixed_id = -1;                // generated fixed-stencil kernel for this table, or -1
   int variant = RLBM_STEP_AUTO;     // RLBM_STEP_AUTO or RLBM_STEP_TABLE
   char err[512] = {0};
@@ -798,6 +813,7 @@ extern "C" int rlbm_destroy(rlbm_ctx* c) {
   if (c->d_tab) (void)hipFree(c->d_tab);
   if (c->d_slots) (void)hipFree(c->d_slots);
   if (c->d_offs) (void)hipFree(c->d_offs);
+  if (c->d_warm) (void)hipFree(c->d_warm);
   delete c->h_tab;
   delete c;
   return RLBM_OK;
@@ -854,6 +870,7 @@ extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const
   hipStream_t s = (hipStream_t)stream;
 
   c->lat = *lat;
+  c->warm = false;
   if (!(c->lat.landau_tol > 0)) c->lat.landau_tol = k.precision == RLBM_FP64 ? 1e-14 : 1e-10;
   if (c->lat.landau_maxit <= 0) c->lat.landau_maxit = 200;
   if (c->lat.landau_method != RLBM_LANDAU_NEWTON && c->lat.landau_method != RLBM_LANDAU_FIXED_POINT)
@@ -956,6 +973,8 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
     a.shift = c->shifted;
     a.offs = c->d_offs + (c->shifted ? RLBM_QMAX : 0);
     a.offs_st = c->d_offs;
+    a.warm = (c->warm && !g) ? c->d_warm : nullptr;
+    a.warm_plane = (long long)c->L.nx * c->L.ny;
     a.fo_rs = c->shifted ? (int)(es * c->L.rs) : 0;
     a.fo_es = c->shifted ? (int)es : 0;
     hipLaunchKernelGGL(fn, dim3(nwg), dim3(kStepBlock), 0, s, a);
@@ -1060,7 +1079,30 @@ extern "C" int rlbm_set_landau_guess(rlbm_ctx* c, const rlbm_mlp* m) {
   if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
   if (m && c->h_tab->c.precision != RLBM_FP32_DEV)
     return fail(c, RLBM_EINVAL, "the learned guess is available for float32 deviation storage");
+  if (m && c->warm) return fail(c, RLBM_EINVAL, "the learned guess and the warm start are exclusive");
   c->guess = m;
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_set_warm_start(rlbm_ctx* c, int enable) {
+  if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
+  if (!enable) {
+    c->warm = false;
+    return RLBM_OK;
+  }
+  if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_set_warm_start before rlbm_init_fields");
+  if (c->guess) return fail(c, RLBM_EINVAL, "the learned guess and the warm start are exclusive");
+  const size_t need = (size_t)3 * c->L.nx * c->L.ny;
+  if (c->warm_cap < need) {
+    if (c->d_warm) HIPCHECK(c, hipFree(c->d_warm));
+    c->d_warm = nullptr;
+    c->warm_cap = 0;
+    HIPCHECK(c, hipMalloc((void**)&c->d_warm, need * sizeof(float)));
+    c->warm_cap = need;
+  }
+  // zero frames: the first step starts as without the warm start
+  HIPCHECK(c, hipMemset(c->d_warm, 0, need * sizeof(float)));
+  c->warm = true;
   return RLBM_OK;
 }
 

@@ -125,6 +125,9 @@ struct RlbmStepArgs {
   int landau_method;   // RLBM_LANDAU_*
   const RlbmTable* tab;
   RlbmSlot* slots;     // one per block (logical index)
+  // warm start: (eps, u_x, u_y) planes of nx ny floats, or nullptr
+  float* warm;
+  long long warm_plane;
   // learned Landau guess (kernels with the guess only)
   const unsigned short* mlp_frag;
   const float* mlp_bias;

@@ -31,6 +31,7 @@ EXPORTS = ["rlbm_init_stencil", "rlbm_solve_stencil", "rlbm_class_table", "rlbm_
            "rlbm_get_health", "rlbm_step_count", "rlbm_save_state", "rlbm_load_state",
            "rlbm_last_error", "rlbm_eos_temperature_host", "rlbm_mlp_create", "rlbm_mlp_destroy",
            "rlbm_mlp_train_step", "rlbm_mlp_predict", "rlbm_mlp_get_params", "rlbm_set_landau_guess",
+           "rlbm_set_warm_start",
            "rlbm_landau_guess_fields", "rlbm_batch_create", "rlbm_batch_destroy", "rlbm_batch_population_bytes",
            "rlbm_batch_sites", "rlbm_batch_init", "rlbm_batch_step_persistent", "rlbm_batch_moments",
            "rlbm_batch_get_health", "rlbm_set_step_variant", "rlbm_step_kernel"]
@@ -111,6 +112,7 @@ def lib():
     L.rlbm_mlp_predict.argtypes = [vp, vp, ci, vp, vp]
     L.rlbm_mlp_get_params.argtypes = [vp, fp, fp]
     L.rlbm_set_landau_guess.argtypes = [vp, vp]
+    L.rlbm_set_warm_start.argtypes = [vp, ci]
     L.rlbm_landau_guess_fields.argtypes = [vp, vp, vp]
     L.rlbm_batch_create.argtypes = [ctypes.POINTER(vp), ci, ctypes.POINTER(vp), ci, ctypes.POINTER(Problem), cd, ci]
     L.rlbm_batch_destroy.argtypes = [vp]
@@ -324,6 +326,11 @@ class Solver:
         """Start every Landau solve from the network's guess (None: plain start)."""
         self._mlp = mlp
         _check(lib().rlbm_set_landau_guess(self.ctx, mlp.h if mlp is not None else None), self.ctx)
+
+    def set_warm_start(self, enable=True):
+        """Start every Landau solve from the frame each site converged to in
+        the previous step (exclusive with the learned guess)."""
+        _check(lib().rlbm_set_warm_start(self.ctx, int(bool(enable))), self.ctx)
 
     def landau_guess_fields(self):
         torch = self.torch
