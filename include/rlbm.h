@@ -159,7 +159,7 @@ typedef struct {
   double eta_over_s, T_R_GeV, n_unit_fm3, dx_fm;
   double landau_tol;     /* target relative accuracy of eps and u (0: 1e-14
                             for FP64, 1e-10 otherwise) */
-  int landau_maxit;      /* iteration cap (0: 200) */
+  int landau_maxit;      /* iteration cap (0: 200; at most 10^6, else RLBM_EINVAL) */
   int landau_method;     /* RLBM_LANDAU_NEWTON: Newton on the characteristic
                             polynomial det(l I - T eta) from l = T^00, then u
                             from the spatial rows; RLBM_LANDAU_FIXED_POINT:
@@ -176,6 +176,9 @@ typedef struct {
  * nx*ny each).  popA and popB (device, pop_bytes each, at least
  * rlbm_population_bytes()) become the ping-pong state.  The step counter is
  * reset and the health flags cleared.  Errors: RLBM_EINVAL, RLBM_EHIP.
+ * Descriptions that are invalid by themselves are rejected before the
+ * context changes; a later failure (layout limits, HIP errors) leaves the
+ * context without fields (rlbm_step then returns RLBM_ESTATE).
  */
 int rlbm_init_fields(rlbm_ctx* ctx, const rlbm_lattice_desc* lat, const double* n, const double* T,
                      const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,

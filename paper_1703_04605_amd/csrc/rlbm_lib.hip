@@ -64,16 +64,29 @@ __device__ __forceinline__ typename Traits<P>::S to_store(typename Traits<P>::A 
 // Reduces health flags and Landau iteration counts over the wave into the
 // wave's own slot (one slot per wave of the persistent grid: no atomics, no
 // races).
+// Reduction over the 64 lanes of a wave (all active) for a commutative,
+// associative op with identity 0: within each row of 16 lanes by DPP lane
+// permutations (quad swaps, then rotations by 4 and 8), then over the four
+// rows' first lanes.
+template <class Op>
+__device__ __forceinline__ unsigned wave_reduce(unsigned v, Op op) {
+  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false));  // row_ror:4
+  v = op(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false));  // row_ror:8
+  const unsigned r0 = (unsigned)__builtin_amdgcn_readlane((int)v, 0);
+  const unsigned r1 = (unsigned)__builtin_amdgcn_readlane((int)v, 16);
+  const unsigned r2 = (unsigned)__builtin_amdgcn_readlane((int)v, 32);
+  const unsigned r3 = (unsigned)__builtin_amdgcn_readlane((int)v, 48);
+  return op(op(r0, r1), op(r2, r3));
+}
+
 __device__ __forceinline__ void wave_stats(RlbmSlot* slots, int gw, unsigned flags, unsigned iters_max,
                                            unsigned iters_sum) {
-  unsigned fl = flags, mx = iters_max;
-  unsigned long long sm = iters_sum;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    fl |= __shfl_xor(fl, off);
-    mx = max(mx, (unsigned)__shfl_xor(mx, off));
-    sm += __shfl_xor(sm, off);
-  }
+  // (a wave's iteration sum, at most 64 (maxit + 1), fits 32 bits)
+  const unsigned fl = wave_reduce(flags, [](unsigned a, unsigned b) { return a | b; });
+  const unsigned mx = wave_reduce(iters_max, [](unsigned a, unsigned b) { return max(a, b); });
+  const unsigned long long sm = wave_reduce(iters_sum, [](unsigned a, unsigned b) { return a + b; });
   if ((threadIdx.x & 63) == 0) {
     RlbmSlot s = slots[gw];
     s.flags |= fl;
@@ -557,7 +570,7 @@ k_step(RlbmStepArgs a) {
   }
 
   // ghost copies are needed only near the lattice edges (uniform test)
-  const unsigned ym = ghost_mask(y, L.ny, L.Sy, L.bc_y);
+  const unsigned ym = (y < L.Sy || y >= L.ny - L.Sy) ? ghost_mask(y, L.ny, L.Sy, L.bc_y) : 0u;
   const bool xedge = x0 < L.Sx || x0 + kWave > L.nx - L.Sx;
   if (xedge || ym != 0u) {
     S* __restrict__ dst = (S*)a.dst;
@@ -869,12 +882,15 @@ extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const
   if (pop_bytes < need) return fail(c, RLBM_EINVAL, "population buffer too small");
   hipStream_t s = (hipStream_t)stream;
 
+  if (lat->landau_maxit > 1000000) return fail(c, RLBM_EINVAL, "landau_maxit above 10^6");
+  if (lat->landau_method != RLBM_LANDAU_NEWTON && lat->landau_method != RLBM_LANDAU_FIXED_POINT)
+    return fail(c, RLBM_EINVAL, "invalid Landau method");
+  // from here on the context is being rebuilt: a failure leaves it without fields
+  c->have_fields = false;
   c->lat = *lat;
   c->warm = false;
   if (!(c->lat.landau_tol > 0)) c->lat.landau_tol = k.precision == RLBM_FP64 ? 1e-14 : 1e-10;
   if (c->lat.landau_maxit <= 0) c->lat.landau_maxit = 200;
-  if (c->lat.landau_method != RLBM_LANDAU_NEWTON && c->lat.landau_method != RLBM_LANDAU_FIXED_POINT)
-    return fail(c, RLBM_EINVAL, "invalid Landau method");
   c->buf[0] = popA;
   c->buf[1] = popB;
   c->pop_bytes = pop_bytes;

@@ -51,10 +51,10 @@ def test_single_site_is_a_fixed_point(precision):
 
 def test_rejects_invalid_lattices_before_any_device_work():
     """Empty lattices, a 1D stencil on more than one row, more than 2^31 - 1
-    sites, 2^31 or more stored elements, and tau <= 1/2 all return
-    RLBM_EINVAL; the context then has no fields, so a step returns
-    RLBM_ESTATE.  The checks precede every device access (the buffers passed
-    here are far smaller than the sizes claimed)."""
+    sites, 2^31 or more stored elements, tau <= 1/2 and an iteration cap
+    above 10^6 all return RLBM_EINVAL; a context without fields then returns
+    RLBM_ESTATE from a step.  The checks precede every device access (the
+    buffers passed here are far smaller than the sizes claimed)."""
     import torch
     from paper_1703_04605_amd import rlbm
     L = rlbm.lib()
@@ -74,5 +74,24 @@ def test_rejects_invalid_lattices_before_any_device_work():
     lat = rlbm.LatticeDesc(8, 2, 0, 0, rlbm.TAU_CONST, 1.0, 0, 0, 0, 0, 0.0, 0, 0)
     rc = L.rlbm_init_fields(s1.ctx, ctypes.byref(lat), f[0].data_ptr(), f[1].data_ptr(), f[2].data_ptr(),
                             f[3].data_ptr(), pa.data_ptr(), pb.data_ptr(), 1 << 20, None)
+    assert rc == rlbm.RLBM_EINVAL
+    assert L.rlbm_step(s.ctx, 1, None) == rlbm.RLBM_ESTATE
+    # an iteration cap above 10^6 is rejected; a re-initialisation that fails
+    # at the layout limit leaves a context that had fields without them
+    from tests.helpers import to_dev
+    g = to_dev(workloads.random_smooth(16, 8, seed=1))
+    s.init_fields(*g)
+    nb = int(s.population_bytes(16, 8))     # real buffers of the claimed size for this case
+    qa = torch.zeros(nb, dtype=torch.uint8, device="cuda:0")
+    qb = torch.zeros(nb, dtype=torch.uint8, device="cuda:0")
+    lat = rlbm.LatticeDesc(16, 8, 0, 0, rlbm.TAU_CONST, 1.0, 0, 0, 0, 0, 0.0, 2000000, 0)
+    rc = L.rlbm_init_fields(s.ctx, ctypes.byref(lat), g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(),
+                            g[3].data_ptr(), qa.data_ptr(), qb.data_ptr(), nb, None)
+    assert rc == rlbm.RLBM_EINVAL
+    s.step(1)                       # rejected before the context changed: still usable
+    lat = rlbm.LatticeDesc(32768, 32768, 0, 0, rlbm.TAU_CONST, 1.0, 0, 0, 0, 0, 0.0, 0, 0)
+    rc = L.rlbm_init_fields(s.ctx, ctypes.byref(lat), f[0].data_ptr(), f[1].data_ptr(), f[2].data_ptr(),
+                            f[3].data_ptr(), pa.data_ptr(), pb.data_ptr(), int(s.population_bytes(32768, 32768)),
+                            None)
     assert rc == rlbm.RLBM_EINVAL
     assert L.rlbm_step(s.ctx, 1, None) == rlbm.RLBM_ESTATE
