@@ -182,7 +182,15 @@ __device__ __forceinline__ unsigned ghost_mask(int x, int n, int S, int bc) {
   unsigned m = 0;
   for (int i = 0; i < 2 * S; ++i) {
     const int c = i < S ? i - S : n + (i - S);
-    const int src = bc == RLBM_BC_PERIODIC ? ((c % n) + n) % n : min(max(c, 0), n - 1);
+    int src;
+    if (bc == RLBM_BC_PERIODIC) {
+      // one wrap when n >= S; lattices smaller than the stencil's reach take
+      // the remainder
+      src = c < 0 ? c + n : (c >= n ? c - n : c);
+      if (src < 0 || src >= n) src = ((c % n) + n) % n;
+    } else {
+      src = min(max(c, 0), n - 1);
+    }
     if (src == x) m |= 1u << i;
   }
   return m;
