@@ -512,6 +512,9 @@ k_step(RlbmStepArgs a) {
   // the Landau solve, which would re-fetch the rows)
 #pragma unroll
   for (int k = 0; k < 9; ++k) asm volatile("" : "+v"(m[k]));
+  // past its pulls, a wave issues ahead of waves still waiting for theirs, so
+  // it finishes and frees its slot sooner
+  __builtin_amdgcn_s_setprio(2);
   double md[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) md[k] = (P == RLBM_FP64) ? (double)m[k] : SC::ref_mom(tb, k) + (double)m[k];
