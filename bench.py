@@ -117,7 +117,7 @@ def time_batched(steps=500):
     h = b.health()
     return {"mlups": b.sites * steps / (ms * 1e-3) / 1e6, "ms": ms, "sites": int(b.sites), "steps": steps,
             "launches": 1, "landau_iter_mean": h["iter_sum"] / (b.sites * steps), "health_flags": h["flags"],
-            "note": "one workgroup per problem; cache-resident (2 x 11.8 MB of populations), not HBM-bound"}
+            "note": "one 1024-thread workgroup per problem; cache-resident (2 x 11.8 MB of populations), not HBM-bound"}
 
 
 def calibration_copy(nbytes=1 << 28):

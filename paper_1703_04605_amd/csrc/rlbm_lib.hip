@@ -1163,7 +1163,7 @@ extern "C" int rlbm_landau_guess_fields(rlbm_ctx* c, float* out, void* stream) {
 
 namespace rlbm {
 
-constexpr int kBatchBlock = 512;
+constexpr int kBatchBlock = 1024;
 constexpr int kBatchQ = 24;  // classes of a 1D stencil
 
 struct RlbmBatchProblem {
