@@ -7,7 +7,9 @@ populations as float32 deviations from a rest-frame equilibrium (float64
 Landau frame, EOS and projections).  The plain float64 path and the scaled
 float16 path are timed on the same workload for comparison.
 
-Prints one JSON line (see the design doc for the fields).
+Prints one JSON line: the headline MLUPS (value), its HBM-roofline fraction
+and measured traffic (roofline), the oracle's CPU rate on a bounded sample
+(cpu_baseline), and every other path of the method under paths.
 """
 import argparse
 import hashlib
@@ -171,8 +173,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-problem workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
