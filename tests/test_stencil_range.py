@@ -1,0 +1,47 @@
+"""Working mbar ranges of the configured stencils (host library), with the
+edge of the paper's 133-population stencil checked against the oracle's own
+quadrature solve.  Sec. III.D states that second-order stencils reach down
+to mbar = 0.35; the ranges are drawn as bars in Fig. 5."""
+import pytest
+
+import workloads
+from oracle import quadrature as quad
+from paper_1703_04605_amd import stencil_range as sr
+
+
+def _ranges(name):
+    return sr.working_ranges(workloads.STENCILS[name]["bases"])
+
+
+def _contains(ranges, z):
+    return any(a <= z <= b for a, b in ranges)
+
+
+def test_configured_stencils_work_at_their_mass():
+    for name in ("zeta036", "zeta1", "zeta5", "zeta10"):
+        st = workloads.STENCILS[name]
+        assert _contains(_ranges(name), st["zeta"]), name
+
+
+def test_lowest_stencil_edge_is_at_the_papers_limit():
+    """The 133-population stencil of Fig. 6 works from just above 0.35 (the
+    paper's second-order limit) and the oracle agrees on both sides of the
+    library's edge: a positive-weight window at 0.365 (the same one), none
+    at 0.355."""
+    r = _ranges("zeta036")
+    lo = min(a for a, _ in r)
+    assert 0.35 <= lo <= 0.36, r
+    b = workloads.STENCILS["zeta036"]["bases"]
+    from paper_1703_04605_amd import rlbm
+    info = rlbm.solve_stencil(b, 0.365)
+    w = quad.positive_window(b, 0.365, 0.1486, 0.14905, grid=20, zoom=8, dps=30)
+    assert w is not None
+    assert abs(float(w[0]) - info["v0_lo"]) < 1e-9 and abs(float(w[1]) - info["v0_hi"]) < 1e-9
+    assert quad.positive_window(b, 0.355, 0.1486, 0.14905, grid=20, zoom=8, dps=30) is None
+    assert not sr.works(b, 0.355) and sr.works(b, 0.365)
+
+
+def test_g1_to_g6_range():
+    """G1..G6 (the paper's m/T_R = 5 example): usable from about 4 upward."""
+    r = _ranges("zeta5")
+    assert _contains(r, 5.0) and _contains(r, 10.0) and not _contains(r, 3.0), r
