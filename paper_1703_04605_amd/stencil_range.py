@@ -50,3 +50,31 @@ def working_ranges(bases, lo=0.2, hi=40.0, points=121, tol=1e-3):
             out.append((start, end))
             start = None
     return out
+
+
+def base_vectors(max_norm2):
+    """Base vectors (a, b, c), a >= b >= c >= 0, 0 < a^2 + b^2 + c^2 <= max_norm2:
+    one per velocity group of App. C (the group is the vector's orbit under
+    the cube's symmetries)."""
+    out = []
+    a = 1
+    while a * a <= max_norm2:
+        for b in range(a + 1):
+            for c in range(b + 1):
+                if 0 < a * a + b * b + c * c <= max_norm2:
+                    out.append((a, b, c))
+        a += 1
+    return sorted(out, key=lambda v: (v[0] ** 2 + v[1] ** 2 + v[2] ** 2, v))
+
+
+def search(mbar, max_norm2=18):
+    """Six-group stencils {(0,0,0)} + five groups with |n|^2 <= max_norm2 that
+    work at mbar, each as a list of base vectors (about 10 ms per candidate;
+    11,628 candidates for max_norm2 = 18)."""
+    import itertools
+    out = []
+    for c in itertools.combinations(base_vectors(max_norm2), 5):
+        cand = [(0, 0, 0)] + list(c)
+        if works(cand, mbar):
+            out.append(cand)
+    return out

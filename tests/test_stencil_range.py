@@ -45,3 +45,13 @@ def test_g1_to_g6_range():
     """G1..G6 (the paper's m/T_R = 5 example): usable from about 4 upward."""
     r = _ranges("zeta5")
     assert _contains(r, 5.0) and _contains(r, 10.0) and not _contains(r, 3.0), r
+
+
+def test_searched_stencils_close_the_gaps():
+    """Two stencils found by stencil_range.search (groups with |n|^2 <= 18)
+    work inside the gaps that the configured stencils leave."""
+    a = [(0, 0, 0), (1, 0, 0), (2, 2, 2), (4, 0, 0), (3, 2, 2), (4, 1, 0)]
+    b = [(0, 0, 0), (2, 0, 0), (2, 1, 1), (2, 2, 0), (2, 2, 1), (3, 0, 0)]
+    assert all(sr.works(a, z) for z in (0.66, 0.8, 0.95))
+    assert all(sr.works(b, z) for z in (1.1, 1.3, 1.6, 5.0))
+    assert not sr.works(a, 0.62)
