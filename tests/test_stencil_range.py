@@ -55,3 +55,13 @@ def test_searched_stencils_close_the_gaps():
     assert all(sr.works(a, z) for z in (0.66, 0.8, 0.95))
     assert all(sr.works(b, z) for z in (1.1, 1.3, 1.6, 5.0))
     assert not sr.works(a, 0.62)
+
+
+def test_base_vectors_are_the_group_table():
+    """The search's groups (one base vector a >= b >= c >= 0 per group) are
+    exactly the App. C groups up to the same |n|^2 (oracle's table)."""
+    from oracle import groups
+    table = {tuple(sorted(groups.base_of(g), reverse=True)) for g in groups.GROUPS}
+    for n2 in (18, 29, 45):
+        want = {b for b in table if 0 < sum(c * c for c in b) <= n2}
+        assert set(sr.base_vectors(n2)) == want, n2
