@@ -285,11 +285,26 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
       set_err(err, errlen, "no v0 with all weights positive in the search interval");
       return RLBM_ENOSTENCIL;
     }
-    ld step = (b - a) / G;
-    ld l_in = best, r_in = best;
-    while (l_in - step > lo && st.min_weight(l_in - step) > 0) l_in -= step;
-    while (r_in + step < hi && st.min_weight(r_in + step) > 0) r_in += step;
-    ld l_out = std::max(l_in - step, lo), r_out = std::min(r_in + step, hi);
+    // bracket each edge by steps that double from the last grid spacing (after
+    // deep zooming that spacing can be far below the window's width), then bisect
+    const ld step0 = std::max((b - a) / G, (hi - lo) * 1e-15L);
+    ld l_in = best, l_out = lo, r_in = best, r_out = hi;
+    for (ld s = step0; best - s > lo; s *= 2) {
+      if (st.min_weight(best - s) > 0) {
+        l_in = best - s;
+      } else {
+        l_out = best - s;
+        break;
+      }
+    }
+    for (ld s = step0; best + s < hi; s *= 2) {
+      if (st.min_weight(best + s) > 0) {
+        r_in = best + s;
+      } else {
+        r_out = best + s;
+        break;
+      }
+    }
     for (int it = 0; it < 100; ++it) {
       ld mid = 0.5L * (l_in + l_out);
       if (st.min_weight(mid) > 0) l_in = mid; else l_out = mid;
