@@ -57,6 +57,21 @@ def test_searched_stencils_close_the_gaps():
     assert not sr.works(a, 0.62)
 
 
+def test_larger_groups_close_the_last_gap():
+    """No stencil of groups with |n|^2 <= 18 works at mbar = 0.615; one of
+    groups up to |n|^2 = 27 (46 populations) does, over [0.49, 1.18], and the
+    oracle's own window search at 0.615 gives the library's window."""
+    from paper_1703_04605_amd import rlbm
+    c = [(0, 0, 0), (3, 3, 0), (5, 0, 0), (5, 1, 0), (3, 3, 3), (5, 1, 1)]
+    assert all(sr.works(c, z) for z in (0.5, 0.582, 0.615, 0.652, 0.8, 1.0, 1.15))
+    assert not sr.works(c, 0.47) and not sr.works(c, 1.2)
+    info = rlbm.solve_stencil(c, 0.615)
+    assert info["q"] == 46
+    w = quad.positive_window(c, 0.615, 0.1912, 0.1921, grid=20, zoom=8, dps=30)
+    assert w is not None
+    assert abs(float(w[0]) - info["v0_lo"]) < 1e-9 and abs(float(w[1]) - info["v0_hi"]) < 1e-9
+
+
 def test_base_vectors_are_the_group_table():
     """The search's groups (one base vector a >= b >= c >= 0 per group) are
     exactly the App. C groups up to the same |n|^2 (oracle's table)."""
