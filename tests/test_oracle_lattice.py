@@ -132,19 +132,3 @@ def test_outflow_keeps_uniform_state():
     f0 = m.f.copy()
     m.step(5)
     assert np.abs(m.f - f0).max() < 1e-14 * np.abs(f0).max()
-
-
-def test_eta_over_s_relaxation_time():
-    """tau from eta/s (Sec. IV): eta = (2/3) P (tau - dt/2), tau = tau_f v0/dx,
-    s = 4n - n ln(n/n_eq).  Check the relation by inverting it."""
-    units = {"T_R_GeV": 0.35, "n_unit_fm3": 5.43 / 0.35, "dx_fm": 0.008}
-    n, T = np.array([1.0, 0.11]), np.array([1.0, 0.5714])
-    v0, es = 0.24, 0.1
-    tau = L.tau_from_eta_over_s(n, T, es, v0, units)
-    n_phys = n * units["n_unit_fm3"]
-    T_phys = T * 0.35
-    P = n_phys * T_phys
-    neq = 16 * T_phys**3 / (np.pi**2 * L.HBARC_GEV_FM**3)
-    s = 4 * n_phys - n_phys * np.log(n_phys / neq)
-    eta = (2.0 / 3.0) * P * (tau - 0.5) * units["dx_fm"] / v0      # GeV/fm^2 * fm ... (physical tau_f - dt/2)
-    assert np.allclose(eta / (s * L.HBARC_GEV_FM), es, rtol=1e-14)
