@@ -1,15 +1,31 @@
 """Benchmark of the relativistic lattice Boltzmann time step on one MI355X.
 
-Workload (default): the 2D periodic Taylor-Green-type vortex, 1024 x 1024
-sites, zeta = m/T_R = 1 (44 population classes), peak speed 0.3, 1% noise on
-n and T, tau = 1, the full 2000-step horizon.  The headline path stores
-populations as float32 deviations from a rest-frame equilibrium (float64
-Landau frame, EOS and projections).  The plain float64 path and the scaled
-float16 path are timed on the same workload for comparison.
+Headline: the learned Landau-frame guess inside a sheared flow
+(Kelvin-Helmholtz), 2048 x 2048 periodic sites, zeta = m/T_R = 1 (44
+population classes), shear +-0.4 across tanh layers 8 cells wide with a
+seeded sinusoidal perturbation of amplitude 0.01, tau = 1.5, populations
+stored as float32 deviations from a rest-frame equilibrium, the network's
+guess followed by fixed-point Landau iterations to |d eps|/eps < 1e-10, 3000
+steps.  value = site updates per second / 1e6 of that path, timed with HIP
+events on the stream the kernels run on, populations resident in HBM.
 
-Prints one JSON line: the headline MLUPS (value), its HBM-roofline fraction
-and measured traffic (roofline), the oracle's CPU rate on a bounded sample
-(cpu_baseline), and every other path of the method under paths.
+Every other measured path sits under ``paths``, each with its rate, HBM
+fraction and its per-field deviation from the float64 path on the same
+workload:
+  * sheared_flow_2048: the same flow without the guess (fixed point from
+    u = 0, Newton), with the warm start, and in float64;
+  * sheared_flow_4096_fp16: 4096 x 4096 sheared flows in scaled float16 for
+    zeta = 0.36, 1, 5, 5000 steps, against float64 runs of the same flows;
+  * taylor_green_1024: the 1024^2 vortex in float32, float16 and float64 over
+    its 2000-step horizon (float32 accuracy gate 1e-5; the float32 buffers
+    only partly exceed the 256 MB Infinity Cache, so this rate is cache
+    assisted);
+  * batched_riemann: 64 independent 1D shock tubes, 500 steps, one launch;
+  * riemann_800: the 800 x 1 shock tube (float64, eta/s = 0.1, 500 steps;
+    launch bound);
+  * copy: a device-to-device copy, the achievable HBM ceiling.
+cpu_baseline times the float64 oracle on the host's cores on strips of the
+headline workload.
 """
 import argparse
 import hashlib
@@ -23,9 +39,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 ELEM = {"fp64": 8, "fp32": 4, "fp16": 2}
+FIELDS = ("n", "eps", "T", "P", "ux", "uy")
 STEP_KERNEL_SOURCES = ["paper_1703_04605_amd/csrc/rlbm_lib.hip", "paper_1703_04605_amd/csrc/rlbm_device.h",
                        "paper_1703_04605_amd/csrc/rlbm_tables.h", "paper_1703_04605_amd/csrc/rlbm_mlp.h",
-                       "paper_1703_04605_amd/csrc/bessel_ratio_coeffs.h", "paper_1703_04605_amd/csrc/gen_fixed_stencils.cpp"]
+                       "paper_1703_04605_amd/csrc/bessel_ratio_coeffs.h",
+                       "paper_1703_04605_amd/csrc/gen_fixed_stencils.cpp"]
+
+# relaxation times at which the sheared flows stay healthy over their full
+# horizons (at tau = 1 the roll-up loses positivity within ~200 steps, in the
+# float64 oracle as on the GPU)
+TAU_KH2048 = 1.5
+TAU_KH4096 = {"zeta036": 3.0, "zeta1": 3.0, "zeta5": 6.0}
 
 
 def kernel_source_hash():
@@ -35,8 +59,8 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision, nx, ny):
-    """HBM bytes per launch of the step kernel from the committed rocprofv3
+def measured_traffic(key):
+    """HBM bytes per launch of a step kernel from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
     if not os.path.exists(path):
@@ -44,12 +68,13 @@ def measured_traffic(precision, nx, ny):
     d = json.load(open(path))
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    e = d.get("entries", {}).get(f"{precision}_{nx}x{ny}")
+    e = d.get("entries", {}).get(key)
     return None if e is None else e.get("hbm_bytes_per_launch")
 
 
-def time_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton", guess=None, variant="auto",
-              warm=False):
+def run_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton", guess=None, variant="auto",
+             warm=False, keep=True):
+    """Runs one path; returns (record, fields after warmup + steps as numpy)."""
     import torch
     from paper_1703_04605_amd import rlbm
     s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=2, precision=precision)
@@ -72,43 +97,81 @@ def time_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton", gu
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
     h = s.health()
-    return s, ms, wall, h
+    sites = s.nx * s.ny
+    q = s.info["q"]
+    ms_step = ms / steps
+    rec = {"mlups": sites * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms_step,
+           "hbm_gbs": 2 * q * ELEM[precision] * sites / (ms_step * 1e-3) / 1e9,
+           "landau_iter_mean": h["iter_sum"] / (sites * steps), "landau_iter_max": h["iter_max"],
+           "health_flags": h["flags"], "kernel": s.step_kernel(), "wall_s": wall, "classes": q}
+    rec["hbm_frac"] = rec["hbm_gbs"] / HBM_PEAK_GBS
+    out = {k: v.cpu().numpy() for k, v in s.moments().items()} if keep else None
+    del s
+    torch.cuda.synchronize()
+    return rec, out
+
+
+def field_errors(a, b, vnorm=None):
+    """max |a - b| / max |b| per field; velocities optionally normalised by a
+    given speed instead (fields whose own maximum is tiny)."""
+    import numpy as np
+    res = {}
+    for k in FIELDS:
+        scale = float(np.abs(b[k]).max())
+        if vnorm is not None and k in ("ux", "uy"):
+            scale = vnorm
+        res[k] = float(np.abs(a[k] - b[k]).max() / (scale if scale > 0 else 1.0))
+    return res
 
 
 def train_guess(st, size=256, steps=400):
-    """The learned Landau guess, trained by the library's kernels on moments of
-    Taylor-Green and Kelvin-Helmholtz runs it produces itself."""
+    """The learned Landau guess, trained by the library's kernels on moment /
+    frame pairs the library produces on the three training workloads: the
+    Taylor-Green vortex, a sheared flow and the batched shock tubes."""
     import torch
     import workloads
     from paper_1703_04605_amd import rlbm, learned_guess
     from tests.helpers import to_dev
-    X, Y = [], []
-    for k, gen in enumerate((workloads.taylor_green(size, size, seed=11),
-                             workloads.kelvin_helmholtz(size, size, seed=12))):
+    X, Y, counts = [], [], {}
+    for k, (name, gen, tau) in enumerate((("taylor_green", workloads.taylor_green(size, size, seed=11), 1.0),
+                                          ("sheared_flow", workloads.kelvin_helmholtz(size, size, seed=12), 1.5))):
         s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=2, precision="fp32")
-        s.init_fields(*to_dev(gen), tau=1.0)
+        s.init_fields(*to_dev(gen), tau=tau)
         x, y = learned_guess.collect(s, steps=60, every=10, max_sites=32768, seed=k)
         X.append(x)
         Y.append(y)
+        counts[name] = int(x.shape[0])
+    b, _ = batched(nprob=16, seed=7, lmax=1024)
+    smp = b.step(100, sample_every=20).reshape(-1, 12)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    idx = torch.randperm(smp.shape[0], generator=g)[:65536].to(smp.device)
+    smp = smp[idx]
+    X.append(smp[:, :9].contiguous())
+    Y.append(smp[:, 9:12].contiguous())
+    counts["batched_riemann"] = int(smp.shape[0])
+    del b
     X, Y = torch.cat(X), torch.cat(Y)
     net = rlbm.MLP(learned_guess.init_params(seed=0), learned_guess.normalisation(X, Y), max_batch=4096)
+    t0 = time.perf_counter()
     losses = learned_guess.train(net, X, Y, steps=steps, batch=4096, lr=2e-3)
-    return net, losses[0], losses[-1]
+    return net, {"first": losses[0], "last": losses[-1], "adam_steps": steps, "batch": 4096,
+                 "samples": counts, "train_s": time.perf_counter() - t0}
+
+
+def batched(nprob=64, seed=0, lmax=4096):
+    import workloads
+    from tests.helpers import build_batch
+    problems, fields = workloads.batched_riemann(nprob=nprob, seed=seed, lmax=lmax)
+    return build_batch(problems, fields), problems
 
 
 def time_batched(steps=500):
-    """64 independent quasi-1D shock tubes (lengths 256..4096, mbar snapped to
-    0.36/1/5/10, eta/s 0.05..0.5, pressure ratios 2..50), 500 steps in one
-    persistent launch, float32 deviation storage."""
+    """64 independent quasi-1D shock tubes (mbar drawn continuously, each with
+    its own stencil), 500 steps in one cooperative launch."""
     import torch
-    import workloads
-    from paper_1703_04605_amd import rlbm
-    problems, fields = workloads.batched_riemann(nprob=64, seed=0)
-    names = sorted({p["stencil_name"] for p in problems})
-    stencils = [rlbm.Solver(workloads.STENCILS[nm]["bases"], workloads.STENCILS[nm]["zeta"],
-                            workloads.STENCILS[nm]["v0"], dim=1, precision="fp32") for nm in names]
-    b = rlbm.Batch(stencils, [dict(p, stencil=names.index(p["stencil_name"])) for p in problems])
-    b.init(*[torch.tensor(a, dtype=torch.float64, device="cuda") for a in fields])
+    t0 = time.perf_counter()
+    b, problems = batched()
+    setup = time.perf_counter() - t0
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
@@ -117,200 +180,235 @@ def time_batched(steps=500):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     h = b.health()
+    occ = b.occupancy()
+    bands = {}
+    for p in problems:
+        bands[p["band"]] = bands.get(p["band"], 0) + 1
     return {"mlups": b.sites * steps / (ms * 1e-3) / 1e6, "ms": ms, "sites": int(b.sites), "steps": steps,
-            "launches": 1, "landau_iter_mean": h["iter_sum"] / (b.sites * steps), "health_flags": h["flags"],
-            "note": "one 1024-thread workgroup per problem; cache-resident (2 x 11.8 MB of populations), not HBM-bound"}
+            "launches": 1, "landau_iter_mean": h["iter_sum"] / (b.sites * steps),
+            "landau_iter_max": h["iter_max"], "health_flags": h["flags"], "occupancy": occ,
+            "waves": occ["workgroups"] * 4, "waves_per_simd": occ["workgroups"] * 4 / 1024.0,
+            "stencil_bands": bands, "zeta_range": [min(p["zeta"] for p in problems), max(p["zeta"] for p in problems)],
+            "stencil_setup_s": setup,
+            "note": "float32 deviations, one stencil per problem at its own mbar; the two population buffers "
+                    f"(2 x {b.pop[0].numel() / 1e6:.1f} MB) stay in the caches, so the rate is not HBM bound"}
 
 
-def calibration_copy(nbytes=1 << 28):
-    """A plain device copy of known size, for scaling the HBM byte counters."""
+def time_riemann_800(steps=500):
+    import torch
+    import workloads
+    from paper_1703_04605_amd import rlbm
+    from tests.helpers import to_dev
+    st = workloads.STENCILS["zeta1"]
+    fields, tau = workloads.riemann_1d(800)
+    s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=1, precision="fp64")
+    s.init_fields(*to_dev(fields), bc=("outflow", "periodic"), tau=tau)
+    s.step(10)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return {"mlups": 800 * steps / (ms * 1e-3) / 1e6, "ms_per_step": ms / steps, "steps": steps,
+            "health_flags": s.health()["flags"], "note": "800 sites: one launch per step, launch bound"}
+
+
+def copy_bandwidth(nbytes=4 << 30, reps=10):
+    """Device-to-device copy of nbytes, bytes read plus written per second."""
     import torch
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1)
-    torch.cuda.synchronize()
     b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"gbs": 2 * nbytes / (ms * 1e-3) / 1e9, "bytes": nbytes, "ms": ms}
 
 
-def cpu_baseline(st, nx, target_s=12.0):
-    """The FP64 oracle (numpy, one thread) on a bounded sample of the same
-    workload: a 64-row strip of the lattice, as many steps as fit ~target_s."""
-    import numpy as np
-    import workloads
+def _oracle_worker(args):
+    """One host core: the float64 oracle (projected classes) on a strip of
+    the headline workload for about target_s seconds."""
+    nx, rows, row0, target_s = args
     from threadpoolctl import threadpool_limits
+    import workloads
     from oracle import lattice as L
-    rows = 64
-    n, T, ux, uy = workloads.taylor_green(nx, nx, seed=0)
+    st = workloads.STENCILS["zeta1"]
+    n, T, ux, uy = workloads.kelvin_helmholtz(nx, nx, seed=0)
+    sl = slice(row0, row0 + rows)
     with threadpool_limits(limits=1):
         ps = L.build_stencil(st["bases"], st["zeta"], st["v0"], mode="projected", dim=2)
-        m = L.Model(ps, nx, rows, tau=1.0)
-        m.init_equilibrium(n[:rows], T[:rows], ux[:rows], uy[:rows])
+        m = L.Model(ps, nx, rows, tau=TAU_KH2048)
+        m.init_equilibrium(n[sl], T[sl], ux[sl], uy[sl])
         t0 = time.perf_counter()
         steps = 0
         while time.perf_counter() - t0 < target_s or steps == 0:
             m.step(1)
             steps += 1
         dt = time.perf_counter() - t0
-    return {"value": nx * rows * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": f"{nx}x{rows} strip of the {nx}x{nx} workload, {steps} steps, projected classes, "
-                      f"numpy float64, {dt:.1f} s"}
+    return nx * rows * steps, dt, steps
+
+
+def cpu_baseline(nx=2048, rows=8, target_s=15.0):
+    """The float64 oracle on every host core of this machine's share (at most
+    16), one process per core, each stepping its own periodic strip of the
+    headline workload; aggregate site updates per second."""
+    import multiprocessing as mp
+    cores = min(16, len(os.sched_getaffinity(0)))
+    ctx = mp.get_context("spawn")
+    jobs = [(nx, rows, (i * rows * 7) % (nx - rows), target_s) for i in range(cores)]
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, jobs)
+    wall = time.perf_counter() - t0
+    rate = sum(u / dt for u, dt, _ in res)
+    steps = [s for _, _, s in res]
+    return {"value": rate / 1e6, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} processes, each the float64 oracle (numpy, projected classes, one thread) on its "
+                      f"own periodic {nx} x {rows} strip of the {nx}^2 sheared flow for {min(steps)}-{max(steps)} "
+                      f"steps (~{target_s:.0f} s); rate summed over processes (pool wall {wall:.0f} s)"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--steps", type=int, default=3000, help="timed steps of the headline path")
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--size", type=int, default=1024)
-    ap.add_argument("--stencil", default="zeta1")
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "fp16"])
-    ap.add_argument("--no-compare", action="store_true", help="skip the other precision paths")
+    ap.add_argument("--only", default=None,
+                    help="run a single path of the headline workload (fp32_guess_fixed_point, fp32_fixed_point, "
+                         "fp32, fp64, ...) and print its record, e.g. for a profiler")
+    ap.add_argument("--no-compare", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-guess", action="store_true", help="skip the learned-guess paths")
-    ap.add_argument("--no-warm", action="store_true", help="skip the warm-start paths")
-    ap.add_argument("--calibration-copy", action="store_true", help="also run a 256 MiB device copy")
-    ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-problem workload")
+    ap.add_argument("--no-fp16-4096", action="store_true", help="skip the 4096^2 float16 flows")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding is not implemented)", file=sys.stderr)
         sys.exit(2)
 
+    # the oracle's processes start before this process touches the GPU
+    cpu = None if (args.no_cpu_baseline or args.only) else cpu_baseline()
+
     import numpy as np
     import torch
     import workloads
     from tests.helpers import to_dev
 
-    st = workloads.STENCILS[args.stencil]
-    nx = ny = args.size
-    fields = to_dev(workloads.taylor_green(nx, ny, seed=0))
-    if args.calibration_copy:
-        calibration_copy()
+    st = workloads.STENCILS["zeta1"]
+    N = 2048
+    kh = to_dev(workloads.kelvin_helmholtz(N, N, seed=0))
+    net, training = train_guess(st)
+    W, K = args.warmup, args.steps
 
-    s, ms, wall, h = time_path(st, fields, args.precision, args.steps, args.warmup)
-    q = s.info["q"]
-    sites = nx * ny
-    ms_step = ms / args.steps
-    mlups = sites * args.steps / (ms * 1e-3) / 1e6
-    alg_bytes = 2 * q * ELEM[args.precision] * sites
-    achieved = alg_bytes / (ms_step * 1e-3) / 1e9
-    traffic = measured_traffic(args.precision, nx, ny)
-    out_hp = {k: v.cpu().numpy() for k, v in s.moments().items()}
-    iters_mean = h["iter_sum"] / (sites * args.steps)
-    kernel = s.step_kernel()
-    del s
+    if args.only:
+        p = args.only
+        rec, _ = run_path(st, kh, p.split("_")[0], K, W, tau=TAU_KH2048,
+                          landau="fixed_point" if p.endswith("fixed_point") else "newton",
+                          guess=net if "guess" in p else None, warm="warm" in p, keep=False)
+        print(json.dumps({"path": p, **rec}))
+        return
 
-    paths = {args.precision: {"mlups": mlups, "ms_per_step": ms_step, "hbm_frac": achieved / HBM_PEAK_GBS,
-                              "landau_iter_mean": iters_mean, "landau_iter_max": h["iter_max"],
-                              "health_flags": h["flags"], "kernel": kernel}}
+    head, o_head = run_path(st, kh, "fp32", K, W, tau=TAU_KH2048, landau="fixed_point", guess=net)
+    paths = {}
     if not args.no_compare:
-        for key in ("fp64", "fp32", "fp16", "fp64_fixed_point", "fp32_fixed_point", "fp32_table", "fp16_table"):
-            p = key.split("_")[0]
-            landau = "fixed_point" if key.endswith("fixed_point") else "newton"
-            variant = "table" if key.endswith("table") else "auto"
-            if key == args.precision:
-                continue
-            s2, ms2, _, h2 = time_path(st, fields, p, args.steps, args.warmup, landau=landau, variant=variant)
-            m2 = sites * args.steps / (ms2 * 1e-3) / 1e6
-            ab = 2 * q * ELEM[p] * sites / (ms2 / args.steps * 1e-3) / 1e9
-            o2 = {k: v.cpu().numpy() for k, v in s2.moments().items()}
-            paths[key] = {"mlups": m2, "ms_per_step": ms2 / args.steps, "hbm_frac": ab / HBM_PEAK_GBS,
-                        "landau_iter_mean": h2["iter_sum"] / (sites * args.steps),
-                        "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"], "kernel": s2.step_kernel()}
-            if key == "fp64":
-                # deviation of the headline path from the float64 GPU path (itself
-                # parity-tested against the oracle) after the full horizon
-                paths[args.precision]["max_rel_err_vs_fp64_path"] = {
-                    k: float(np.abs(out_hp[k] - o2[k]).max() / np.abs(o2[k]).max())
-                    for k in ("n", "eps", "T", "P", "ux", "uy")}
-            del s2
-        if "fp64" in paths:
-            paths["speedup_vs_fp64"] = mlups / paths["fp64"]["mlups"]
-    if not args.no_guess:
-        net, l0, l1 = train_guess(st)
-        for key, landau in (("fp32_guess", "newton"), ("fp32_guess_fixed_point", "fixed_point")):
-            s2, ms2, _, h2 = time_path(st, fields, "fp32", args.steps, args.warmup, landau=landau, guess=net)
-            m2 = sites * args.steps / (ms2 * 1e-3) / 1e6
-            ab = 2 * q * 4 * sites / (ms2 / args.steps * 1e-3) / 1e9
-            o2 = {k: v.cpu().numpy() for k, v in s2.moments().items()}
-            paths[key] = {"mlups": m2, "ms_per_step": ms2 / args.steps, "hbm_frac": ab / HBM_PEAK_GBS,
-                          "landau_iter_mean": h2["iter_sum"] / (sites * args.steps),
-                          "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"],
-                          "kernel": s2.step_kernel()}
-            # the same step kernel (fixed-stencil or table-driven, whichever the
-            # guided run used) without the guess, and the fastest unguided path
-            same = "auto" if paths[key]["kernel"] == "fixed" else "table"
-            s3, ms3, _, h3 = time_path(st, fields, "fp32", args.steps, args.warmup, landau=landau, variant=same)
-            m3 = sites * args.steps / (ms3 * 1e-3) / 1e6
-            o3 = {k: v.cpu().numpy() for k, v in s3.moments().items()}
-            del s3
-            paths[key]["unguided_same_kernel_mlups"] = m3
-            paths[key]["unguided_same_kernel_landau_iter_mean"] = h3["iter_sum"] / (sites * args.steps)
-            paths[key]["speedup_vs_unguided_same_kernel"] = m2 / m3
-            paths[key]["max_rel_err_vs_unguided_same_kernel"] = {
-                k: float(np.abs(o2[k] - o3[k]).max() / np.abs(o3[k]).max()) for k in ("n", "eps", "T", "P", "ux", "uy")}
-            ref_key = "fp32" if landau == "newton" else "fp32_fixed_point"
-            if ref_key == args.precision or ref_key in paths:
-                paths[key]["speedup_vs_fastest_unguided"] = m2 / paths[ref_key]["mlups"]
-            if "fp64" in paths:
-                paths[key]["speedup_vs_fp64"] = m2 / paths["fp64"]["mlups"]
-            del s2
-        paths["guess_training_loss"] = {"first": l0, "last": l1}
-    if not args.no_warm and not args.no_compare:
-        # Landau solve started from each site's frame of the previous step,
-        # against the same kernel started plainly
-        for key, landau in (("fp32_warm", "newton"), ("fp32_warm_fixed_point", "fixed_point")):
-            s2, ms2, _, h2 = time_path(st, fields, "fp32", args.steps, args.warmup, landau=landau, warm=True)
-            m2 = sites * args.steps / (ms2 * 1e-3) / 1e6
-            ab = 2 * q * 4 * sites / (ms2 / args.steps * 1e-3) / 1e9
-            o2 = {k: v.cpu().numpy() for k, v in s2.moments().items()}
-            kern = s2.step_kernel()
-            del s2
-            s3, ms3, _, h3 = time_path(st, fields, "fp32", args.steps, args.warmup, landau=landau)
-            m3 = sites * args.steps / (ms3 * 1e-3) / 1e6
-            o3 = {k: v.cpu().numpy() for k, v in s3.moments().items()}
-            del s3
-            paths[key] = {"mlups": m2, "ms_per_step": ms2 / args.steps, "hbm_frac": ab / HBM_PEAK_GBS,
-                          "landau_iter_mean": h2["iter_sum"] / (sites * args.steps),
-                          "landau_iter_max": h2["iter_max"], "health_flags": h2["flags"], "kernel": kern,
-                          "extra_bytes_per_site": 24,
-                          "plain_same_kernel_mlups": m3,
-                          "plain_landau_iter_mean": h3["iter_sum"] / (sites * args.steps),
-                          "speedup_vs_plain": m2 / m3,
-                          "max_rel_err_vs_plain": {k: float(np.abs(o2[k] - o3[k]).max() / np.abs(o3[k]).max())
-                                                   for k in ("n", "eps", "T", "P", "ux", "uy")}}
-            gkey = "fp32_guess" if landau == "newton" else "fp32_guess_fixed_point"
-            if gkey in paths:
-                paths[key]["speedup_vs_learned_guess"] = m2 / paths[gkey]["mlups"]
+        flow = {"fp32_guess_fixed_point": head}
+        runs = {"fp32_guess_fixed_point": o_head}
+        for key, prec, landau, g, warm in (("fp32_fixed_point", "fp32", "fixed_point", None, False),
+                                           ("fp32_guess", "fp32", "newton", net, False),
+                                           ("fp32", "fp32", "newton", None, False),
+                                           ("fp32_warm_fixed_point", "fp32", "fixed_point", None, True),
+                                           ("fp32_warm", "fp32", "newton", None, True),
+                                           ("fp64_fixed_point", "fp64", "fixed_point", None, False),
+                                           ("fp64", "fp64", "newton", None, False)):
+            flow[key], runs[key] = run_path(st, kh, prec, K, W, tau=TAU_KH2048, landau=landau, guess=g, warm=warm)
+        vmax = 0.4
+        for key in flow:
+            if key != "fp64":
+                flow[key]["max_rel_err_vs_fp64"] = field_errors(runs[key], runs["fp64"], vnorm=vmax)
+        for g, plain in (("fp32_guess_fixed_point", "fp32_fixed_point"), ("fp32_guess", "fp32"),
+                         ("fp32_warm_fixed_point", "fp32_fixed_point"), ("fp32_warm", "fp32")):
+            flow[g]["max_rel_err_vs_" + plain] = field_errors(runs[g], runs[plain], vnorm=vmax)
+            flow[g]["speedup_vs_" + plain] = flow[g]["mlups"] / flow[plain]["mlups"]
+            flow[g]["iteration_ratio_vs_" + plain] = flow[g]["landau_iter_mean"] / flow[plain]["landau_iter_mean"]
+        flow["fp32_guess_fixed_point"]["speedup_vs_fp64"] = head["mlups"] / flow["fp64"]["mlups"]
+        flow["fp32_fixed_point"]["speedup_vs_fp64_fixed_point"] = (flow["fp32_fixed_point"]["mlups"]
+                                                                   / flow["fp64_fixed_point"]["mlups"])
+        del runs
+        paths["sheared_flow_2048"] = {"workload": f"Kelvin-Helmholtz {N}^2, zeta 1, tau {TAU_KH2048}, "
+                                                  f"{K} steps after {W}", "velocity_error_scale": vmax, **flow}
+        paths["guess_training"] = training
 
-    if not args.no_batched and not args.no_compare:
-        paths["batched_riemann_64x500"] = time_batched()
-    cpu = None if args.no_cpu_baseline else cpu_baseline(st, nx)
+        # Taylor-Green 1024^2 over its 2000-step horizon
+        tg = to_dev(workloads.taylor_green(1024, 1024, seed=0))
+        tgp, tgo = {}, {}
+        for key, prec, var in (("fp64", "fp64", "auto"), ("fp32", "fp32", "auto"), ("fp32_table", "fp32", "table"),
+                               ("fp16", "fp16", "auto")):
+            tgp[key], tgo[key] = run_path(st, tg, prec, 2000, 0, tau=1.0, variant=var)
+        for key in ("fp32", "fp32_table", "fp16"):
+            tgp[key]["max_rel_err_vs_fp64"] = field_errors(tgo[key], tgo["fp64"])
+        del tgo, tg
+        paths["taylor_green_1024"] = {"workload": "Taylor-Green 1024^2, zeta 1, tau 1, 2000 steps",
+                                      "cache_assisted": True, **tgp}
+
+        # 4096^2 sheared flows in scaled float16 for three masses
+        if not args.no_fp16_4096:
+            big = {}
+            khb = to_dev(workloads.kelvin_helmholtz(4096, 4096, seed=0))
+            for name in ("zeta036", "zeta1", "zeta5"):
+                sb = workloads.STENCILS[name]
+                tau = TAU_KH4096[name]
+                r16, o16 = run_path(sb, khb, "fp16", 5000, 0, tau=tau)
+                r64, o64 = run_path(sb, khb, "fp64", 5000, 0, tau=tau)
+                r16["max_rel_err_vs_fp64"] = field_errors(o16, o64, vnorm=0.4)
+                big[name] = {"zeta": sb["zeta"], "tau": tau, "fp16": r16, "fp64": r64,
+                             "fp16_speedup_vs_fp64": r16["mlups"] / r64["mlups"]}
+                del o16, o64
+                torch.cuda.empty_cache()
+            del khb
+            paths["sheared_flow_4096_fp16"] = {"workload": "Kelvin-Helmholtz 4096^2, 5000 steps", **big}
+        paths["batched_riemann"] = time_batched()
+        paths["riemann_800"] = time_riemann_800()
+    copy = copy_bandwidth()
+    paths["copy"] = copy
+
+    q = head["classes"]
+    sites = N * N
+    alg = 2 * q * 4 * sites
     res = {
         "metric": "MLUPS (site updates per second / 1e6) of the RLBM time step",
-        "value": mlups,
+        "value": head["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "fp16": "f16"}[args.precision],
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"taylor_green_{nx}x{ny}_{args.stencil}", "nx": nx, "ny": ny,
+        "config": {"workload": f"kelvin_helmholtz_{N}x{N}_zeta1_fp32_learned_guess", "nx": N, "ny": N,
                    "zeta": st["zeta"], "v0": st["v0"], "population_classes": q,
-                   "storage": {"fp64": "float64", "fp32": "float32 deviation",
-                               "fp16": "scaled float16 deviation"}[args.precision],
-                   "tau": 1.0, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                   "storage": "float32 deviation", "landau": "learned guess, then fixed point to 1e-10",
+                   "tau": TAU_KH2048, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": head["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": head["hbm_gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(f"fp32_guess_{N}x{N}"),
+                     "algorithmic_bytes_per_launch": alg, "copy_gbs": copy["gbs"],
+                     "copy_frac": head["hbm_gbs"] / copy["gbs"], "kernel": head["kernel"]},
         "cpu_baseline": cpu,
         "paths": paths,
-        "wall_s_timed_region": wall,
+        "landau_iter_mean": head["landau_iter_mean"],
+        "health_flags": head["health_flags"],
+        "wall_s_timed_region": head["wall_s"],
     }
     print(json.dumps(res))
 

@@ -25,9 +25,10 @@
  *   - Population buffers and field buffers are owned by the caller; the
  *     library keeps the raw pointers until the next rlbm_init_fields() or
  *     rlbm_destroy().  The context and its stencil tables are owned by the
- *     library.  Only rlbm_init_stencil (the constant tables) and
- *     rlbm_init_fields (a small per-block health array) allocate device
- *     memory; the time-stepping entry points never do.
+ *     library.  Only rlbm_init_stencil (the constant tables),
+ *     rlbm_init_fields (a small per-tile health array), the warm start and
+ *     the batched and network set-up calls allocate device memory; the
+ *     time-stepping entry points never do.
  */
 #ifndef RLBM_H
 #define RLBM_H
@@ -164,7 +165,11 @@ typedef struct {
                             polynomial det(l I - T eta) from l = T^00, then u
                             from the spatial rows; RLBM_LANDAU_FIXED_POINT:
                             eps = T^00 - T^0i u_i, u_i = (T^0i - T^ij u_j)/eps
-                            from u = 0, until |d eps| <= tol eps, |d u| <= tol */
+                            from u = 0, until |d eps| <= tol eps, |d u| <= tol
+                            (3D lattices: Newton only) */
+  int nz;                /* 3D stencils (dim 3): sites along z (>= 1); must
+                            be 0 or 1 for 1D and 2D stencils */
+  int bc_z;              /* 3D stencils: RLBM_BC_* along z */
 } rlbm_lattice_desc;
 
 #define RLBM_LANDAU_NEWTON 0
@@ -176,13 +181,23 @@ typedef struct {
  * nx*ny each).  popA and popB (device, pop_bytes each, at least
  * rlbm_population_bytes()) become the ping-pong state.  The step counter is
  * reset and the health flags cleared.  Errors: RLBM_EINVAL, RLBM_EHIP.
- * Descriptions that are invalid by themselves are rejected before the
- * context changes; a later failure (layout limits, HIP errors) leaves the
- * context without fields (rlbm_step then returns RLBM_ESTATE).
+ * Invalid descriptions (the checks of rlbm_check_lattice, NULL or too small
+ * buffers) are rejected before the context changes; a HIP failure after that
+ * leaves the context without fields (rlbm_step then returns RLBM_ESTATE).
  */
 int rlbm_init_fields(rlbm_ctx* ctx, const rlbm_lattice_desc* lat, const double* n, const double* T,
                      const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
                      void* stream);
+
+/*
+ * Host-only (no HIP call): checks a lattice description against a stencil
+ * description exactly as rlbm_init_fields does before it touches the device
+ * (sizes, boundary rules, relaxation time, Landau options, and the layout's
+ * limits: fewer than 2^31 stored elements and class byte offsets below
+ * 2^31).  RLBM_OK, or RLBM_EINVAL / RLBM_ENOSTENCIL with the reason in
+ * rlbm_last_error(NULL).
+ */
+int rlbm_check_lattice(const rlbm_stencil_desc* desc, const rlbm_lattice_desc* lat);
 
 /*
  * Advances nsteps time steps (collide, then stream; eq.
@@ -300,8 +315,10 @@ int rlbm_set_warm_start(rlbm_ctx* ctx, int enable);
  * lattice with outflow ends, float32 deviation storage and tau from eta/s
  * (rlbm_lattice_desc's RLBM_TAU_ETA_OVER_S rule), using one of the given
  * stencil contexts (rlbm_init_stencil with dim 1, RLBM_FP32_DEV, at most 24
- * classes; they must outlive the batch).  One workgroup advances one problem
- * through all steps of a call, with a workgroup barrier between steps.
+ * classes; they must outlive the batch).  The sites of all problems are cut
+ * into tiles of 64 sites, one wave each; a cooperative launch spread over the
+ * whole device advances every tile through all steps of a call, with a
+ * grid-wide barrier between steps.
  */
 typedef struct {
   int nx;                 /* sites */
@@ -325,6 +342,10 @@ int rlbm_batch_init(rlbm_batch* b, const double* n, const double* T, const doubl
  * T^0y, T^xx, T^xy, T^yy, eps, u_x, u_y): training pairs for the learned
  * guess; layout [t / sample_every][site][12]. */
 int rlbm_batch_step_persistent(rlbm_batch* b, int nsteps, int sample_every, float* samples, void* stream);
+/* The cooperative grid of rlbm_batch_step_persistent (host, nullable):
+ * workgroups of 256 threads launched, the most the device holds at once for
+ * this kernel (the grid never exceeds it), and the number of 64-site tiles. */
+int rlbm_batch_occupancy(const rlbm_batch* b, int* workgroups, int* resident_limit, int* tiles);
 /* pre-collision fields (device float64, concatenated; any may be NULL) */
 int rlbm_batch_moments(rlbm_batch* b, double* n, double* eps, double* T, double* P, double* ux, void* stream);
 /* OR of the health flags and Landau iteration statistics of all problems

@@ -42,9 +42,11 @@ HBARC_GEV_FM = 0.1973269804
 class PopulationSet:
     """disp [Q, 2] in-plane displacement, p [Q, d] momenta (d = 4 full,
     3 for 2D classes (p0, px, py), 2 for 1D classes (p0, px)), M [Q, 14]
-    = sum over members of w_i J^(k)(p_i)."""
+    = sum over members of w_i J^(k)(p_i); disp3 [Q, 3] the full 3D
+    displacement (full stencils only)."""
 
-    def __init__(self, disp, p, M, mbar, v0, coeffs, weights, group_index):
+    def __init__(self, disp, p, M, mbar, v0, coeffs, weights, group_index, disp3=None):
+        self.disp3 = None if disp3 is None else np.asarray(disp3, dtype=np.int64)
         self.disp = np.asarray(disp, dtype=np.int64)
         self.p = np.asarray(p, dtype=np.float64)
         self.M = np.asarray(M, dtype=np.float64)
@@ -85,7 +87,7 @@ def build_stencil(bases, mbar, v0, mode="full", dim=2, weights=None, dps=50):
     J = np.array(evaluate_printed(mom, mbar))            # [14, Q3]
     Mfull = (wt[None, :] * J).T                          # [Q3, 14]
     if mode == "full":
-        return PopulationSet(vec[:, :2], mom, Mfull, mbar, v0, coeffs, weights, gid)
+        return PopulationSet(vec[:, :2], mom, Mfull, mbar, v0, coeffs, weights, gid, disp3=vec)
     keyc = 2 if dim == 2 else 1
     keys = {}
     for i in range(len(vec)):
@@ -190,6 +192,11 @@ class Model:
         return out
 
     def collide(self):
+        return self._collide_flat().reshape(self.ps.Q, self.ny, self.nx)
+
+    def _collide_flat(self):
+        """Post-collision populations [Q, sites] (Anderson-Witting relaxation
+        toward f^eq of the local Landau frame)."""
         ps = self.ps
         f = self.f.reshape(ps.Q, -1)
         mac = macroscopic(ps, f)
@@ -202,7 +209,7 @@ class Model:
         eta = np.diag([1.0] + [-1.0] * (ps.d - 1))
         pU = ps.p @ eta @ mac["U"].T                      # [Q, S] p_i^mu U_mu
         omega = pU / (ps.p[:, :1] * tau[None, :])
-        return (f - omega * (f - feq)).reshape(ps.Q, self.ny, self.nx)
+        return f - omega * (f - feq)
 
     def stream(self, fpost):
         out = np.empty_like(fpost)
@@ -214,6 +221,64 @@ class Model:
             sx = np.mod(sx, self.nx) if self.bc[0] == "periodic" else np.clip(sx, 0, self.nx - 1)
             sy = np.mod(sy, self.ny) if self.bc[1] == "periodic" else np.clip(sy, 0, self.ny - 1)
             out[q] = fpost[q][np.ix_(sy, sx)]
+        return out
+
+    def step(self, nsteps=1):
+        for _ in range(nsteps):
+            self.f = self.stream(self.collide())
+            self.t += 1
+
+
+class Model3D(Model):
+    """A lattice of Nx x Ny x Nz sites with every population of the 3D
+    stencil, f [Q, Nz, Ny, Nx] (Sec. V: the method runs in three dimensions
+    as in two).  bc: (bc_x, bc_y, bc_z), each 'periodic' or 'outflow'.  The
+    collision is the parent's (it works on any population set with full
+    four-momenta); streaming moves population i by its 3D vector n_i."""
+
+    def __init__(self, ps, nx, ny, nz, bc=("periodic", "periodic", "periodic"), tau=1.0):
+        if ps.disp3 is None:
+            raise ValueError("3D lattices need the full stencil (mode='full')")
+        super().__init__(ps, nx, ny, bc=bc[:2], tau=tau)
+        self.nz, self.bc3 = nz, bc
+
+    def init_equilibrium(self, n, T, ux, uy, uz):
+        S = self.nx * self.ny * self.nz
+        n = np.asarray(n, dtype=np.float64).reshape(S)
+        T = np.asarray(T, dtype=np.float64).reshape(S)
+        ux, uy, uz = (np.asarray(a, dtype=np.float64).reshape(S) for a in (ux, uy, uz))
+        g = 1.0 / np.sqrt(1.0 - ux * ux - uy * uy - uz * uz)
+        U4 = np.stack([g, g * ux, g * uy, g * uz], axis=-1)
+        self.f = equilibrium(self.ps, n, T, U4).reshape(self.ps.Q, self.nz, self.ny, self.nx)
+        self.t = 0
+
+    def fields(self, f=None):
+        f = self.f if f is None else f
+        mac = macroscopic(self.ps, f.reshape(self.ps.Q, -1))
+        U = mac["U"]
+        shp = (self.nz, self.ny, self.nx)
+        out = {k: mac[k].reshape(shp) for k in ("n", "eps", "T", "P")}
+        for a, k in ((1, "ux"), (2, "uy"), (3, "uz")):
+            out[k] = (U[:, a] / U[:, 0]).reshape(shp)
+        N, Tm = mac["N"], mac["Tmn"]
+        raw = [N[:, 0], N[:, 1], N[:, 2], N[:, 3], Tm[:, 0, 0], Tm[:, 0, 1], Tm[:, 0, 2], Tm[:, 0, 3],
+               Tm[:, 1, 1], Tm[:, 1, 2], Tm[:, 1, 3], Tm[:, 2, 2], Tm[:, 2, 3], Tm[:, 3, 3]]
+        out["raw14"] = np.array(raw).reshape((14,) + shp)
+        out["_mac"] = mac
+        return out
+
+    def collide(self):
+        return self._collide_flat().reshape(self.ps.Q, self.nz, self.ny, self.nx)
+
+    def stream(self, fpost):
+        out = np.empty_like(fpost)
+        axes = [(self.nx, self.bc3[0]), (self.ny, self.bc3[1]), (self.nz, self.bc3[2])]
+        for q in range(self.ps.Q):
+            src = []
+            for (n, bc), d in zip(axes, self.ps.disp3[q]):
+                s = np.arange(n) - d
+                src.append(np.mod(s, n) if bc == "periodic" else np.clip(s, 0, n - 1))
+            out[q] = fpost[q][np.ix_(src[2], src[1], src[0])]
         return out
 
     def step(self, nsteps=1):

@@ -25,6 +25,13 @@
 // rows to that accuracy, and the cheapest one (additions plus multiply-adds)
 // is chosen, separately for the moments and for the equilibrium.
 //
+// For float32 storage every coefficient is emitted as a float pair hi + lo
+// (hi its nearest float, lo the float nearest to the remainder): the moments
+// collect the lo products in nine accumulators of their own, and the lo part
+// of the equilibrium is subtracted from f - f^eq before the relaxation.  A
+// float coefficient alone would bias every step by its rounding (about 2^-25
+// relative), and that bias accumulates in the conserved quantities.
+//
 // The output also carries each stencil's table fingerprint; the library uses
 // a generated kernel only for a context whose table has the same fingerprint.
 #include <math.h>
@@ -117,6 +124,11 @@ static std::string flit(ld x) {
   snprintf(b, sizeof b, "%.9ef", (double)(float)x);
   return b;
 }
+
+// A coefficient as float: its nearest float (hi) and, when split, the float
+// nearest to the remainder (lo), so that hi + lo carries it to about 2^-48.
+static ld hi_of(ld x) { return (ld)(float)x; }
+static ld lo_of(ld x, bool split) { return split ? (ld)(float)(x - hi_of(x)) : 0.0L; }
 
 // Orbits of the classes: lists of class indices in canonical member order.
 static std::vector<std::vector<int>> orbits(const RlbmTable& t) {
@@ -251,13 +263,16 @@ struct OrbitPlan {
   std::vector<std::vector<ld>> Cm, Ce;   // coefficients
 };
 
+// Rows of the class loops: for float32 storage the float rows plus their
+// rounding remainders (the row values to about 2^-48), otherwise the float
+// rows as they are.
 static OrbitPlan plan_orbit(const RlbmTable& t, const std::vector<int>& o) {
   const int n = (int)o.size();
   std::vector<std::vector<ld>> Rm, Re;
   for (int j : o) {
     std::vector<ld> rm(9), re(RLBM_NB);
-    for (int k = 0; k < 9; ++k) rm[k] = t.rowmf[j][k];
-    for (int k = 0; k < RLBM_NB; ++k) re[k] = t.rowf[j][k];
+    for (int k = 0; k < 9; ++k) rm[k] = (ld)t.rowmf[j][k] + (ld)t.rowmf_lo[j][k];
+    for (int k = 0; k < RLBM_NB; ++k) re[k] = (ld)t.rowf[j][k] + (ld)t.rowf_lo[j][k];
     Rm.push_back(rm);
     Re.push_back(re);
   }
@@ -290,6 +305,7 @@ static OrbitPlan plan_orbit(const RlbmTable& t, const std::vector<int>& o) {
 
 static std::string gen_struct(const char* sname, const RlbmTable& t) {
   const int Q = t.c.Q;
+  const bool split = t.c.precision == RLBM_FP32_DEV;
   std::vector<OrbitPlan> plans;
   for (auto& o : orbits(t)) plans.push_back(plan_orbit(t, o));
   Emitter em;
@@ -324,45 +340,61 @@ static std::string gen_struct(const char* sname, const RlbmTable& t) {
       for (int k = 0; k < 9; ++k) {
         if (pl.Cm[o][k] == 0 || v[o].zero) continue;
         const ld c = v[o].neg ? -pl.Cm[o][k] : pl.Cm[o][k];
-        em.line("m[" + std::to_string(k) + "] = fmaf(" + v[o].name + ", " + flit(c) + ", m[" + std::to_string(k) +
-                "]);");
+        em.line("m[" + std::to_string(k) + "] = fmaf(" + v[o].name + ", " + flit(hi_of(c)) + ", m[" +
+                std::to_string(k) + "]);");
+        const ld cl = lo_of(c, split);
+        if (cl != 0)
+          em.line("ml[" + std::to_string(k) + "] = fmaf(" + v[o].name + ", " + flit(cl) + ", ml[" +
+                  std::to_string(k) + "]);");
       }
     em.line("}");
   }
   s += "  static __device__ __forceinline__ void moments(const float (&f)[" + std::to_string(Q) +
-       "], float (&m)[9]) {\n" + em.out + "  }\n";
+       "], float (&m)[9], float (&ml)[9]) {\n" + em.out + "  }\n";
   // equilibrium, relaxation and stores, one orbit at a time
   em.out.clear();
   for (auto& pl : plans) {
     const int n = (int)pl.members.size();
     em.line("{  // orbit of class " + std::to_string(pl.members[0]) + " (" + std::to_string(n) + ")");
-    std::vector<Val> g(n);
-    for (int o = 0; o < n; ++o) {
-      std::string e;
-      for (int k = 0; k < RLBM_NB; ++k) {
-        if (pl.Ce[o][k] == 0) continue;
-        if (e.empty()) e = "nb[" + std::to_string(k) + "] * " + flit(pl.Ce[o][k]);
-        else e = "fmaf(nb[" + std::to_string(k) + "], " + flit(pl.Ce[o][k]) + ", " + e + ")";
+    // g = C' nb for the float parts of the coefficients and, when split,
+    // gl for their remainders; the same butterflies take both to the classes
+    auto chain = [&](bool lo, std::vector<Val>& g) {
+      for (int o = 0; o < n; ++o) {
+        std::string e;
+        for (int k = 0; k < RLBM_NB; ++k) {
+          if (pl.Ce[o][k] == 0) continue;
+          const ld c = lo ? lo_of(pl.Ce[o][k], split) : hi_of(pl.Ce[o][k]);
+          if (c == 0) continue;
+          if (e.empty()) e = "nb[" + std::to_string(k) + "] * " + flit(c);
+          else e = "fmaf(nb[" + std::to_string(k) + "], " + flit(c) + ", " + e + ")";
+        }
+        if (e.empty()) continue;
+        g[o].zero = false;
+        g[o].name = em.fresh(lo ? "gl" : "g");
+        em.line("const float " + g[o].name + " = " + e + ";");
       }
-      if (e.empty()) continue;
-      g[o].zero = false;
-      g[o].name = em.fresh("g");
-      em.line("const float " + g[o].name + " = " + e + ";");
-    }
-    for (int i = (int)pl.be.size() - 1; i >= 0; --i) {
-      const int x = pl.be[i].first, y = pl.be[i].second;
-      const Val a = g[x], b = g[y];
-      g[x] = em.addsub(a, b, false);
-      g[y] = em.addsub(a, b, true);
-    }
+      for (int i = (int)pl.be.size() - 1; i >= 0; --i) {
+        const int x = pl.be[i].first, y = pl.be[i].second;
+        const Val a = g[x], b = g[y];
+        g[x] = em.addsub(a, b, false);
+        g[y] = em.addsub(a, b, true);
+      }
+    };
+    std::vector<Val> g(n), gl(n);
+    chain(false, g);
+    chain(true, gl);
+    auto ref = [](const Val& v) { return v.zero ? std::string("0.0f") : (v.neg ? "(-" + v.name + ")" : v.name); };
     for (int i = 0; i < n; ++i) {
       const int j = pl.members[i];
-      std::string feq = g[i].zero ? "0.0f" : (g[i].neg ? "(-" + g[i].name + ")" : g[i].name);
       std::string om = "W0";
       if (t.ny[j] != 0) om = "fmaf(WY, " + flit((ld)t.ny[j]) + ", " + om + ")";
       if (t.nx[j] != 0) om = "fmaf(WX, " + flit((ld)t.nx[j]) + ", " + om + ")";
       const std::string fj = "f[" + std::to_string(j) + "]";
-      em.line(fj + " = fmaf(-(" + om + "), " + fj + " - " + feq + ", " + fj + ");");
+      // f - f^eq is small next to f, so subtracting the remainder part there
+      // keeps it (a correction below half an ulp of f would be lost in f)
+      std::string diff = fj + " - " + ref(g[i]);
+      if (!gl[i].zero) diff = "(" + diff + ") - " + ref(gl[i]);
+      em.line(fj + " = fmaf(-(" + om + "), " + diff + ", " + fj + ");");
       em.line("st.template put<" + std::to_string(j) + ">(" + fj + ");");
     }
     em.line("}");

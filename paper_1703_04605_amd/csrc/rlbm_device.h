@@ -243,6 +243,86 @@ __device__ __forceinline__ void projections(TabPtr tb, double T, double R, doubl
   projections(proj_consts(tb), T, R, U0, Ux, Uy, b);
 }
 
+// Landau frame in 3D, by Newton's method on the characteristic polynomial of
+// the 4 x 4 mixed tensor.  With S(l) = l I + T_s (T_s the spatial block of
+// T^ab) and t = (T^0x, T^0y, T^0z), the block determinant gives
+//   p(l) = det(l I - T eta) = (l - T00) det S(l) + t . adj(S(l)) t,
+// and for a 3 x 3 matrix det S(l) = l^3 + e2 l^2 + e1 l + e0 and
+// adj S(l) = l^2 I + l (e2 I - T_s) + adj(T_s), with e2 = tr T_s, e1 the sum
+// of its principal 2 x 2 minors and e0 = det T_s.  The roots of p are real,
+// so to the right of the largest one p and all its derivatives are positive
+// and Newton from above (T^00 >= eps) decreases monotonically onto eps.  The
+// velocity then solves the spatial rows (eps I + T_s) u = t:
+// u = adj(S(eps)) t / det S(eps).  Returns the iteration count (maxit + 1 if
+// the cap was hit).
+__device__ __forceinline__ int landau_newton3(const double m[14], double thresh, int maxit, double& eps,
+                                              double u[3], double l0) {
+  // m: N0, Nx, Ny, Nz, T00, T0x, T0y, T0z, Txx, Txy, Txz, Tyy, Tyz, Tzz
+  const double T00 = m[4], tx = m[5], ty = m[6], tz = m[7];
+  const double xx = m[8], xy = m[9], xz = m[10], yy = m[11], yz = m[12], zz = m[13];
+  const double axx = yy * zz - yz * yz, ayy = xx * zz - xz * xz, azz = xx * yy - xy * xy;
+  const double axy = xz * yz - xy * zz, axz = xy * yz - xz * yy, ayz = xy * xz - xx * yz;
+  const double e2 = xx + yy + zz, e1 = axx + ayy + azz, e0 = xx * axx + xy * axy + xz * axz;
+  const double t2 = tx * tx + ty * ty + tz * tz;
+  const double Ttx = xx * tx + xy * ty + xz * tz, Tty = xy * tx + yy * ty + yz * tz, Ttz = xz * tx + yz * ty + zz * tz;
+  const double tTt = tx * Ttx + ty * Tty + tz * Ttz;
+  const double Atx = axx * tx + axy * ty + axz * tz, Aty = axy * tx + ayy * ty + ayz * tz,
+               Atz = axz * tx + ayz * ty + azz * tz;
+  const double tAt = tx * Atx + ty * Aty + tz * Atz;
+  const double c1 = e2 * t2 - tTt;
+  double l = l0;
+  if (l != T00) {  // a start below T^00 must lie where p is increasing and convex
+    const double D = fma(fma(l + e2, l, e1), l, e0), Dp = fma(fma(3.0, l, 2.0 * e2), l, e1);
+    const double dp = fma(l - T00, Dp, D) + fma(2.0 * t2, l, c1);
+    if (!(dp > 0.0)) l = T00;
+  }
+  int it = 1;
+  bool done = false;
+  for (; it <= maxit; ++it) {
+    const double D = fma(fma(l + e2, l, e1), l, e0);
+    const double Dp = fma(fma(3.0, l, 2.0 * e2), l, e1);
+    const double p = fma(l - T00, D, fma(fma(t2, l, c1), l, tAt));
+    const double dp = fma(l - T00, Dp, D) + fma(2.0 * t2, l, c1);
+    const double step = div_nr(p, dp);
+    l -= step;
+    if (done) break;
+    if (fabs(step) <= thresh * l) done = true;
+  }
+  const double D = fma(fma(l + e2, l, e1), l, e0);
+  const double inv = rcp_nr(D);
+  // adj(S(eps)) t = eps^2 t + eps (e2 t - T_s t) + adj(T_s) t
+  u[0] = fma(l, fma(l, tx, e2 * tx - Ttx), Atx) * inv;
+  u[1] = fma(l, fma(l, ty, e2 * ty - Tty), Aty) * inv;
+  u[2] = fma(l, fma(l, tz, e2 * tz - Ttz), Atz) * inv;
+  eps = l;
+  return it;
+}
+
+// Projection coefficients of all 14 polynomials (3D lattices; order of
+// Appendix A: 0, 1_0, 1_x, 1_y, 1_z, 2_00, 2_0x, 2_0y, 2_0z, 2_xx, 2_yy,
+// 2_xz, 2_yz, 2_xy, where 2_xx is (p_y^2 - p_z^2)/(2E) and 2_yy is
+// (-2 p_x^2 + p_y^2 + p_z^2)/(2 sqrt 3 E)); the 2D set is these with U_z = 0.
+__device__ __forceinline__ void projections3(const ProjConsts& c, double T, double R, double U0, const double U[3],
+                                             double b[14]) {
+  const double b0 = R * c.inv_zeta;
+  const double q = fma(c.zeta, R, 4.0 * T);
+  b[0] = b0;
+  b[1] = (U0 - c.a1 * b0) * c.invA;
+  b[2] = U[0] * c.invB;
+  b[3] = U[1] * c.invB;
+  b[4] = U[2] * c.invB;
+  b[5] = (q * U0 * U0 - T + c.c1 * U0 + c.c0 * b0) * c.inv_s3C;
+  const double s = (q * U0 - c.d0) * c.invD;
+  b[6] = s * U[0];
+  b[7] = s * U[1];
+  b[8] = s * U[2];
+  b[9] = q * (U[1] * U[1] - U[2] * U[2]) * (0.5 * c.invE);
+  b[10] = q * (U[1] * U[1] + U[2] * U[2] - 2.0 * U[0] * U[0]) * (0.28867513459481288225 * c.invE);
+  b[11] = q * U[0] * U[2] * c.invE;
+  b[12] = q * U[1] * U[2] * c.invE;
+  b[13] = q * U[0] * U[1] * c.invE;
+}
+
 // Relaxation time per site from eta/s (Sec. IV): tau = 1/2 + (3/2)(eta/s) s hbar_c v0/(P dx)
 // with s/P = (4 - ln(n/n_eq))/T in physical units, folded into tk1, tk2.
 __device__ __forceinline__ double tau_eta_over_s(double tk1, double tk2, double n, double T) {

@@ -11,11 +11,13 @@
 // equilibrium from the projections and relaxes (Anderson-Witting), and writes
 // the post-collision values to the other buffer.  Each population value is
 // read once and written once per step, which is the HBM roofline of the step.
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <memory>
 #include <type_traits>
 #include <utility>
 #include <cmath>
@@ -357,6 +359,7 @@ constexpr int kWaitLgkm0 = 0xC07F;
 // Per-class table rows as whole structs, so each is fetched by wide scalar
 // loads (moments: the nine monomials; equilibrium: M_j, n_j).
 template <int P> struct Rows;
+// (ml, el: the rows' rounding remainders, read by float32 storage only)
 template <> struct Rows<RLBM_FP64> {
   struct alignas(16) M { double v[RLBM_ROWMD]; };
   struct alignas(16) E { double v[RLBM_ROWD]; };
@@ -366,6 +369,8 @@ template <> struct Rows<RLBM_FP64> {
   static __device__ __forceinline__ const __attribute__((address_space(4))) E* e(TabPtr t) {
     return (const __attribute__((address_space(4))) E*)t->rowd;
   }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) M* ml(TabPtr t) { return m(t); }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) E* el(TabPtr t) { return e(t); }
 };
 template <> struct Rows<RLBM_FP32_DEV> {
   struct alignas(16) M { float v[RLBM_ROWMF]; };
@@ -375,6 +380,12 @@ template <> struct Rows<RLBM_FP32_DEV> {
   }
   static __device__ __forceinline__ const __attribute__((address_space(4))) E* e(TabPtr t) {
     return (const __attribute__((address_space(4))) E*)t->rowf;
+  }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) M* ml(TabPtr t) {
+    return (const __attribute__((address_space(4))) M*)t->rowmf_lo;
+  }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) E* el(TabPtr t) {
+    return (const __attribute__((address_space(4))) E*)t->rowf_lo;
   }
 };
 template <> struct Rows<RLBM_FP16_DEV> : Rows<RLBM_FP32_DEV> {};
@@ -487,37 +498,55 @@ k_step(RlbmStepArgs a) {
 
   // moments (eq. mj-discrete-second-moment) as one multiply-add per
   // monomial; deviation modes add the exact float64 moments of the reference
+  // float32 storage: m collects the float parts of the rows, ml their
+  // rounding remainders (the rows to about 2^-48; zero in the other modes)
+  constexpr bool kSplit = P == RLBM_FP32_DEV;
   A f[QN];
   A m[9] = {A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0)};
+  A ml[9] = {A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0), A(0)};
   if constexpr (kFixed) {
 #pragma unroll
     for (int j = 0; j < QN; ++j) f[j] = (A)raw[j];
-    Fx::moments(f, m);
+    Fx::moments(f, m, ml);
   } else {
     const auto* rows = Rows<P>::m(tb);
+    const auto* rows_lo = Rows<P>::ml(tb);
     typename Rows<P>::M cur = load_row(rows);
+    typename Rows<P>::M cur_lo = kSplit ? load_row(rows_lo) : cur;
 #pragma unroll
     for (int j = 0; j < QN; ++j) {
       __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
-      const typename Rows<P>::M nxt = load_row(rows + (j + 1 < QN ? j + 1 : j));
+      const int jn = j + 1 < QN ? j + 1 : j;
+      const typename Rows<P>::M nxt = load_row(rows + jn);
+      const typename Rows<P>::M nxt_lo = kSplit ? load_row(rows_lo + jn) : nxt;
       __builtin_amdgcn_sched_barrier(0);
       f[j] = (A)raw[j];
 #pragma unroll
       for (int k = 0; k < 9; ++k) m[k] = fma(f[j], (A)cur.v[k], m[k]);
+      if constexpr (kSplit) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) ml[k] = fma(f[j], (A)cur_lo.v[k], ml[k]);
+      }
       __builtin_amdgcn_sched_barrier(0);
       cur = nxt;
+      cur_lo = nxt_lo;
     }
   }
   // all nine sums are formed here, next to the class values (not sunk past
   // the Landau solve, which would re-fetch the rows)
 #pragma unroll
   for (int k = 0; k < 9; ++k) asm volatile("" : "+v"(m[k]));
+  if constexpr (kSplit) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) asm volatile("" : "+v"(ml[k]));
+  }
   // past its pulls, a wave issues ahead of waves still waiting for theirs, so
   // it finishes and frees its slot sooner
   __builtin_amdgcn_s_setprio(2);
   double md[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) md[k] = (P == RLBM_FP64) ? (double)m[k] : SC::ref_mom(tb, k) + (double)m[k];
+  for (int k = 0; k < 9; ++k)
+    md[k] = (P == RLBM_FP64) ? (double)m[k] : SC::ref_mom(tb, k) + ((double)m[k] + (double)ml[k]);
 
   double e0 = 0.0, ux0 = 0.0, uy0 = 0.0;
   const long long wsite = (long long)y * L.nx + min(x, L.nx - 1);
@@ -557,17 +586,29 @@ k_step(RlbmStepArgs a) {
     Fx::collide(f, nb, W0, WX, WY, st);
   } else {
     const auto* rows = Rows<P>::e(tb);
+    const auto* rows_lo = Rows<P>::el(tb);
     typename Rows<P>::E cur = load_row(rows);
+    typename Rows<P>::E cur_lo = kSplit ? load_row(rows_lo) : cur;
 #pragma unroll
     for (int j = 0; j < QN; ++j) {
       __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
-      const typename Rows<P>::E nxt = load_row(rows + (j + 1 < QN ? j + 1 : j));
+      const int jn = j + 1 < QN ? j + 1 : j;
+      const typename Rows<P>::E nxt = load_row(rows + jn);
+      const typename Rows<P>::E nxt_lo = kSplit ? load_row(rows_lo + jn) : nxt;
       __builtin_amdgcn_sched_barrier(0);
       A feq = nb[0] * (A)cur.v[0];
 #pragma unroll
       for (int k = 1; k < RLBM_NB; ++k) feq = fma(nb[k], (A)cur.v[k], feq);
       const A om = fma(WY, (A)cur.v[RLBM_R_NY], fma(WX, (A)cur.v[RLBM_R_NX], W0));
-      f[j] = fma(-om, f[j] - feq, f[j]);
+      A diff = f[j] - feq;
+      if constexpr (kSplit) {
+        // the remainder part of f^eq, taken off the small difference f - f^eq
+        A feql = nb[0] * (A)cur_lo.v[0];
+#pragma unroll
+        for (int k = 1; k < RLBM_NB; ++k) feql = fma(nb[k], (A)cur_lo.v[k], feql);
+        diff = diff - feql;
+      }
+      f[j] = fma(-om, diff, f[j]);
       const __amdgpu_buffer_rsrc_t r = (j < QMIN || j < Q) ? rs_st : rs_none;
       if constexpr (P == RLBM_FP64)
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, f[j]), r, vst, own[j], 0);
@@ -577,6 +618,7 @@ k_step(RlbmStepArgs a) {
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)f[j]), r, vst, own[j], 0);
       __builtin_amdgcn_sched_barrier(0);
       cur = nxt;
+      cur_lo = nxt_lo;
     }
   }
 
@@ -594,6 +636,306 @@ k_step(RlbmStepArgs a) {
   }
   wave_stats(a.slots, t, active ? mac.flags : 0u, active ? (unsigned)mac.iters : 0u,
              active ? (unsigned)mac.iters : 0u);
+}
+
+// ------------------------------------------------------------------ 3D step
+//
+// 3D lattices (Sec. V: the method runs in three dimensions as in two): every
+// population of the stencil is its own class, moments are the 14 components
+// of N^a and T^ab, the Landau frame has three velocity components (Newton on
+// the quartic characteristic polynomial), the equilibrium takes all 14
+// projections, and streaming moves a population by its 3D vector.  Layout:
+// storage planes z of storage rows y, each row holding the Q class rows of
+// one lattice row (x fastest), with ghost columns, rows and planes of the
+// stencil's reach on every side.  One wave per 64 sites of a row, one buffer
+// descriptor per tile based at the lowest element its pulls reach, per-class
+// byte offsets from the context's table (class offsets in 3D include n_z).
+
+// ghost copies of site (x, y, z) in class row q: every combination of the
+// owner or ghost coordinate on each axis except the owner itself
+template <typename S>
+__device__ __forceinline__ void store_ghosts3(S* __restrict__ q, const RlbmLayout& L, int x, int y, int z,
+                                              unsigned xm, unsigned ym, unsigned zm, S v) {
+  const unsigned zall = (zm << 1) | 1u, yall = (ym << 1) | 1u, xall = (xm << 1) | 1u;
+  for (unsigned mz = zall; mz; mz &= mz - 1) {
+    const int bz = __builtin_ctz(mz);
+    const int cz = bz == 0 ? z : ghost_coord(bz - 1, L.nz, L.Sz);
+    for (unsigned my = yall; my; my &= my - 1) {
+      const int by = __builtin_ctz(my);
+      const int cy = by == 0 ? y : ghost_coord(by - 1, L.ny, L.Sy);
+      const long long row = (long long)(cz + L.GZ) * L.zs + (long long)(cy + L.GY) * L.rs + L.GX;
+      for (unsigned mx = xall; mx; mx &= mx - 1) {
+        const int bx = __builtin_ctz(mx);
+        if (bx == 0 && by == 0 && bz == 0) continue;
+        const int cx = bx == 0 ? x : ghost_coord(bx - 1, L.nx, L.Sx);
+        q[row + cx] = v;
+      }
+    }
+  }
+}
+
+template <int P> struct Rows3;
+template <> struct Rows3<RLBM_FP64> {
+  struct alignas(16) M { double v[RLBM_ROWM3]; };
+  struct alignas(16) E { double v[RLBM_ROW3]; };
+  static __device__ __forceinline__ const __attribute__((address_space(4))) M* m(TabPtr t) {
+    return (const __attribute__((address_space(4))) M*)t->rowm3d;
+  }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) E* e(TabPtr t) {
+    return (const __attribute__((address_space(4))) E*)t->row3d;
+  }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) M* ml(TabPtr t) { return m(t); }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) E* el(TabPtr t) { return e(t); }
+};
+template <> struct Rows3<RLBM_FP32_DEV> {
+  struct alignas(16) M { float v[RLBM_ROWM3]; };
+  struct alignas(16) E { float v[RLBM_ROW3]; };
+  static __device__ __forceinline__ const __attribute__((address_space(4))) M* m(TabPtr t) {
+    return (const __attribute__((address_space(4))) M*)t->rowm3f;
+  }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) E* e(TabPtr t) {
+    return (const __attribute__((address_space(4))) E*)t->row3f;
+  }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) M* ml(TabPtr t) {
+    return (const __attribute__((address_space(4))) M*)t->rowm3f_lo;
+  }
+  static __device__ __forceinline__ const __attribute__((address_space(4))) E* el(TabPtr t) {
+    return (const __attribute__((address_space(4))) E*)t->row3f_lo;
+  }
+};
+template <> struct Rows3<RLBM_FP16_DEV> : Rows3<RLBM_FP32_DEV> {};
+
+constexpr int step3_waves(int qn, int p) { return p == RLBM_FP64 ? (qn <= 60 ? 2 : 1) : (qn <= 60 ? 3 : 2); }
+
+template <int QN, int QMIN, int P>
+__global__ void __launch_bounds__(kStepBlock) __attribute__((amdgpu_waves_per_eu(step3_waves(QN, P))))
+k_step3(RlbmStepArgs a) {
+  using S = typename Traits<P>::S;
+  using A = typename Traits<P>::A;
+  typedef const __attribute__((address_space(4))) unsigned* OffPtr;
+  constexpr bool kSplit = P == RLBM_FP32_DEV;
+  const TabPtr tb = as_tab(a.tab);
+  const RlbmLayout& L = a.L;
+  const int lane = (int)threadIdx.x & (kWave - 1);
+  const int t = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (kStepBlock / kWave) +
+                __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  if (t >= a.ntiles) return;  // whole wave
+  const int Q = tb->c.Q;
+  const int row = t / a.tiles_x;  // z * ny + y
+  const int z = row / L.ny, y = row - z * L.ny;
+  const int x0 = (t - row * a.tiles_x) * kWave;
+  const int x = x0 + lane;
+  const bool active = x < L.nx;
+  const int nvalid = min(kWave, L.nx - x0);
+  const long long lo =
+      (long long)(z + L.GZ - L.Sz) * L.zs + (long long)(y + L.GY - L.Sy) * L.rs + L.GX - L.Sx + x0;
+  const __amdgpu_buffer_rsrc_t rs_ld = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)((const char*)a.src + lo * (long long)sizeof(S)), (short)0, kRecAll, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rs_st = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)((char*)a.dst + lo * (long long)sizeof(S)), (short)0, kRecAll, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rs_none = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)((char*)a.dst + lo * (long long)sizeof(S)), (short)0, 0, kRsrcWord3);
+  const int vld = min(lane, nvalid - 1) * (int)sizeof(S);
+  const int vst = active ? lane * (int)sizeof(S) : kRecOut;
+  const OffPtr pull = (OffPtr)a.offs;
+  const OffPtr own = (OffPtr)a.offs_st;
+
+  // pull: f_i(x, t) = f*_i(x - n_i, t - 1) (exact streaming)
+  S raw[QN];
+#pragma unroll
+  for (int j = 0; j < QN; ++j) {
+    if constexpr (P == RLBM_FP64)
+      raw[j] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs_ld, vld, pull[j], 0));
+    else if constexpr (P == RLBM_FP32_DEV)
+      raw[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs_ld, vld, pull[j], 0));
+    else
+      raw[j] = __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs_ld, vld, pull[j], 0));
+  }
+
+  // the 14 moments (float32 storage: rows plus rounding remainders)
+  A f[QN];
+  A m[RLBM_NB3], ml[RLBM_NB3];
+#pragma unroll
+  for (int k = 0; k < RLBM_NB3; ++k) m[k] = ml[k] = A(0);
+  {
+    const auto* rows = Rows3<P>::m(tb);
+    const auto* rows_lo = Rows3<P>::ml(tb);
+    typename Rows3<P>::M cur = load_row(rows);
+    typename Rows3<P>::M cur_lo = kSplit ? load_row(rows_lo) : cur;
+#pragma unroll
+    for (int j = 0; j < QN; ++j) {
+      __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+      const int jn = j + 1 < QN ? j + 1 : j;
+      const typename Rows3<P>::M nxt = load_row(rows + jn);
+      const typename Rows3<P>::M nxt_lo = kSplit ? load_row(rows_lo + jn) : nxt;
+      __builtin_amdgcn_sched_barrier(0);
+      f[j] = (A)raw[j];
+#pragma unroll
+      for (int k = 0; k < RLBM_NB3; ++k) m[k] = fma(f[j], (A)cur.v[k], m[k]);
+      if constexpr (kSplit) {
+#pragma unroll
+        for (int k = 0; k < RLBM_NB3; ++k) ml[k] = fma(f[j], (A)cur_lo.v[k], ml[k]);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      cur = nxt;
+      cur_lo = nxt_lo;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RLBM_NB3; ++k) asm volatile("" : "+v"(m[k]));
+  if constexpr (kSplit) {
+#pragma unroll
+    for (int k = 0; k < RLBM_NB3; ++k) asm volatile("" : "+v"(ml[k]));
+  }
+  __builtin_amdgcn_s_setprio(2);
+  double md[RLBM_NB3];
+#pragma unroll
+  for (int k = 0; k < RLBM_NB3; ++k)
+    md[k] = (P == RLBM_FP64) ? (double)m[k] : tb->c.ref_mom3[k] + ((double)m[k] + (double)ml[k]);
+
+  // Landau frame, density, EOS
+  unsigned flags = 0;
+  double eps, u[3];
+  const int iters = landau_newton3(md, newton_thresh(a.landau_tol), a.landau_maxit, eps, u, md[4]);
+  if (iters > a.landau_maxit) flags |= RLBM_H_LANDAU;
+  const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  if (!(u2 < 1.0)) flags |= RLBM_H_SUPERLUMINAL;
+  const double gamma = rsqrt_nr(1.0 - u2);
+  const double n = gamma * (md[0] - u[0] * md[1] - u[1] * md[2] - u[2] * md[3]);
+  if (!(n > 0.0) || !(eps > 0.0)) flags |= RLBM_H_RANGE;
+  const double e = div_nr(eps, n);
+  const double T = eos_temperature_tab(tb, e, tb->c.zeta, flags);
+  const double R = (e - 3.0 * T) * tb->c.inv_zeta;
+  if (!isfinite(T) || !isfinite(eps) || !isfinite(n) || !isfinite(R)) flags |= RLBM_H_NAN;
+  const double tau = a.tau_mode == RLBM_TAU_CONST ? a.tau : tau_eta_over_s(a.tk1, a.tk2, n, T);
+  double b[RLBM_NB3];
+  const double U[3] = {gamma * u[0], gamma * u[1], gamma * u[2]};
+  projections3(proj_consts(tb), T, R, gamma, U, b);
+  const double w0 = a.tau_mode == RLBM_TAU_CONST ? gamma * a.inv_tau : div_nr(gamma, tau);
+  const double v0 = tb->c.v0;
+  A nb[RLBM_NB3];
+#pragma unroll
+  for (int k = 0; k < RLBM_NB3; ++k) nb[k] = (A)(n * b[k] - (P == RLBM_FP64 ? 0.0 : tb->c.nb_ref3[k]));
+  const A W0 = (A)w0, WX = (A)(-w0 * v0 * u[0]), WY = (A)(-w0 * v0 * u[1]), WZ = (A)(-w0 * v0 * u[2]);
+
+  // equilibrium (eq. mj-discrete-feq, all 14 polynomials) and relaxation
+  {
+    const auto* rows = Rows3<P>::e(tb);
+    const auto* rows_lo = Rows3<P>::el(tb);
+    typename Rows3<P>::E cur = load_row(rows);
+    typename Rows3<P>::E cur_lo = kSplit ? load_row(rows_lo) : cur;
+#pragma unroll
+    for (int j = 0; j < QN; ++j) {
+      __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+      const int jn = j + 1 < QN ? j + 1 : j;
+      const typename Rows3<P>::E nxt = load_row(rows + jn);
+      const typename Rows3<P>::E nxt_lo = kSplit ? load_row(rows_lo + jn) : nxt;
+      __builtin_amdgcn_sched_barrier(0);
+      A feq = nb[0] * (A)cur.v[0];
+#pragma unroll
+      for (int k = 1; k < RLBM_NB3; ++k) feq = fma(nb[k], (A)cur.v[k], feq);
+      const A om = fma(WZ, (A)cur.v[RLBM_R3_NZ], fma(WY, (A)cur.v[RLBM_R3_NY], fma(WX, (A)cur.v[RLBM_R3_NX], W0)));
+      A diff = f[j] - feq;
+      if constexpr (kSplit) {
+        A feql = nb[0] * (A)cur_lo.v[0];
+#pragma unroll
+        for (int k = 1; k < RLBM_NB3; ++k) feql = fma(nb[k], (A)cur_lo.v[k], feql);
+        diff = diff - feql;
+      }
+      f[j] = fma(-om, diff, f[j]);
+      const __amdgpu_buffer_rsrc_t r = (j < QMIN || j < Q) ? rs_st : rs_none;
+      if constexpr (P == RLBM_FP64)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, f[j]), r, vst, own[j], 0);
+      else if constexpr (P == RLBM_FP32_DEV)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, f[j]), r, vst, own[j], 0);
+      else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)f[j]), r, vst, own[j], 0);
+      __builtin_amdgcn_sched_barrier(0);
+      cur = nxt;
+      cur_lo = nxt_lo;
+    }
+  }
+
+  // ghost copies near the lattice edges
+  const unsigned zm = (z < L.Sz || z >= L.nz - L.Sz) ? ghost_mask(z, L.nz, L.Sz, L.bc_z) : 0u;
+  const unsigned ym = (y < L.Sy || y >= L.ny - L.Sy) ? ghost_mask(y, L.ny, L.Sy, L.bc_y) : 0u;
+  const bool xedge = x0 < L.Sx || x0 + kWave > L.nx - L.Sx;
+  if (xedge || ym != 0u || zm != 0u) {
+    S* __restrict__ dst = (S*)a.dst;
+    const unsigned xm = xedge ? ghost_mask(x, L.nx, L.Sx, L.bc_x) : 0u;
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < QN; ++j)
+        if (j < Q) store_ghosts3(dst + (long long)j * L.cs, L, x, y, z, xm, ym, zm, (S)f[j]);
+    }
+  }
+  wave_stats(a.slots, t, active ? flags : 0u, active ? (unsigned)iters : 0u, active ? (unsigned)iters : 0u);
+}
+
+// 3D fields and raw moments of the current (pre-collision) state
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_moments3(RlbmMomArgs a, double* __restrict__ uz,
+                                                     double* __restrict__ raw14) {
+  using S = typename Traits<P>::S;
+  const TabPtr tb = as_tab(a.tab);
+  const RlbmLayout& L = a.L;
+  const long long S3 = (long long)L.nx * L.ny * L.nz;
+  const long long site = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (site >= S3) return;
+  const int x = (int)(site % L.nx);
+  const long long yz = site / L.nx;
+  const int y = (int)(yz % L.ny), z = (int)(yz / L.ny);
+  const S* __restrict__ src = (const S*)a.src;
+  double m[RLBM_NB3] = {};
+  for (int j = 0; j < tb->c.Q; ++j) {
+    const int sx = a.shift ? x - tb->nx[j] : x, sy = a.shift ? y - tb->ny[j] : y, sz = a.shift ? z - tb->nz[j] : z;
+    const long long idx = (long long)j * L.cs + (long long)(sz + L.GZ) * L.zs + (long long)(sy + L.GY) * L.rs + sx + L.GX;
+    const double f = (double)to_arith<P>(src[idx], tb, j);
+    for (int k = 0; k < RLBM_NB3; ++k) m[k] = fma(f, tb->rowm3d[j][k], m[k]);
+  }
+  if (P != RLBM_FP64)
+    for (int k = 0; k < RLBM_NB3; ++k) m[k] += tb->c.ref_mom3[k];
+  unsigned flags = 0;
+  double eps, u[3];
+  (void)landau_newton3(m, newton_thresh(a.landau_tol), a.landau_maxit, eps, u, m[4]);
+  const double g = rsqrt_nr(1.0 - u[0] * u[0] - u[1] * u[1] - u[2] * u[2]);
+  const double n = g * (m[0] - u[0] * m[1] - u[1] * m[2] - u[2] * m[3]);
+  const double T = eos_temperature_tab(tb, div_nr(eps, n), tb->c.zeta, flags);
+  if (a.n) a.n[site] = n;
+  if (a.eps) a.eps[site] = eps;
+  if (a.T) a.T[site] = T;
+  if (a.P) a.P[site] = n * T;
+  if (a.ux) a.ux[site] = u[0];
+  if (a.uy) a.uy[site] = u[1];
+  if (uz) uz[site] = u[2];
+  if (raw14)
+    for (int k = 0; k < RLBM_NB3; ++k) raw14[k * S3 + site] = m[k];
+}
+
+// f_i(x, 0) = f_i^eq(n, T, u) on a 3D lattice
+template <int P>
+__global__ void __launch_bounds__(kBlock) k_init3(RlbmInitArgs a, const double* __restrict__ uz) {
+  using S = typename Traits<P>::S;
+  const TabPtr tb = as_tab(a.tab);
+  const RlbmLayout& L = a.L;
+  const long long site = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (site >= (long long)L.nx * L.ny * L.nz) return;
+  const int x = (int)(site % L.nx);
+  const long long yz = site / L.nx;
+  const int y = (int)(yz % L.ny), z = (int)(yz / L.ny);
+  const double n = a.n[site], T = a.T[site];
+  const double u[3] = {a.ux[site], a.uy[site], uz[site]};
+  const double g = 1.0 / sqrt(1.0 - u[0] * u[0] - u[1] * u[1] - u[2] * u[2]);
+  const double U[3] = {g * u[0], g * u[1], g * u[2]};
+  double b[RLBM_NB3];
+  projections3(proj_consts(tb), T, k1k2_ratio(tb->c.zeta / T), g, U, b);
+  S* __restrict__ dst = (S*)a.dst;
+  const long long o = (long long)(z + L.GZ) * L.zs + (long long)(y + L.GY) * L.rs + x + L.GX;
+  for (int j = 0; j < tb->c.Q; ++j) {
+    double fe = 0.0;
+    for (int k = 0; k < RLBM_NB3; ++k) fe = fma(n * b[k] - (P == RLBM_FP64 ? 0.0 : tb->c.nb_ref3[k]), tb->row3d[j][k], fe);
+    dst[(long long)j * L.cs + o] = to_store<P>((typename Traits<P>::A)fe, tb, j);
+  }
 }
 
 // ------------------------------------------------------------------ moments
@@ -768,10 +1110,10 @@ struct rlbm_ctx {
   int cur = 0;
   int shifted = 0;
   long long steps = 0;
-  RlbmSlot* d_slots = nullptr;
-  unsigned* d_offs = nullptr;  // [0, QMAX): in-place byte offsets, [QMAX, 2 QMAX): pull byte offsets
-  int tiles_x = 0, ntiles = 0;  // wave tiles (kWave sites of a row)
-  int nslots = 0;               // health slots: one per tile
+  RlbmSlot* slots = nullptr;    // health slots in use
+  RlbmSlot* d_slots = nullptr;  // library-allocated health slots
+  int nslots = 0;               // capacity of d_slots
+  int tiles_x = 0, ntiles = 0;  // wave tiles (kWave sites of a row); one health slot each
   double tk1 = 0, tk2 = 0;
   const rlbm_mlp* guess = nullptr;
   float* d_warm = nullptr;          // warm-start frames (3 planes of nx ny floats)
@@ -836,7 +1178,6 @@ extern "C" int rlbm_destroy(rlbm_ctx* c) {
   (void)hipDeviceSynchronize();
   if (c->d_tab) (void)hipFree(c->d_tab);
   if (c->d_slots) (void)hipFree(c->d_slots);
-  if (c->d_offs) (void)hipFree(c->d_offs);
   if (c->d_warm) (void)hipFree(c->d_warm);
   delete c->h_tab;
   delete c;
@@ -846,58 +1187,142 @@ extern "C" int rlbm_destroy(rlbm_ctx* c) {
 // Row-interleaved layout: ghost columns padded to 32 elements so every
 // interior class row starts on a 32-element boundary; ghost rows of the max
 // |n_y|; the Q class rows of a lattice row are consecutive.
-static RlbmLayout make_layout(const RlbmConsts& k, int nx, int ny, int bc_x, int bc_y) {
+// 3D lattices stack nz + 2 GZ planes of storage rows (GZ = max |n_z|).
+static RlbmLayout make_layout(const RlbmConsts& k, int nx, int ny, int bc_x, int bc_y, int nz = 1, int bc_z = 0) {
   RlbmLayout L;
   L.nx = nx;
   L.ny = ny;
+  L.nz = nz;
   L.Sx = k.sx_max;
   L.Sy = k.sy_max;
+  L.Sz = k.dim == 3 ? k.sz_max : 0;
   L.GX = (L.Sx + 31) / 32 * 32;
   L.GY = L.Sy;
+  L.GZ = L.Sz;
   L.W = (L.GX + nx + L.Sx + 31) / 32 * 32;
   L.cs = L.W;
   L.rs = (long long)k.Q * L.W;
-  const long long s = (long long)(ny + 2 * L.GY) * L.rs;
+  L.zs = (long long)(ny + 2 * L.GY) * L.rs;
+  const long long s = (long long)(nz + 2 * L.GZ) * L.zs;
   L.total = (s + kPlaneAlign - 1) / kPlaneAlign * kPlaneAlign;
   L.bc_x = bc_x;
   L.bc_y = bc_y;
+  L.bc_z = bc_z;
   return L;
 }
 
 extern "C" size_t rlbm_population_bytes(const rlbm_ctx* c, int nx, int ny) {
-  if (!c || nx <= 0 || ny <= 0) return 0;
+  if (!c || nx <= 0 || ny <= 0 || c->h_tab->c.dim == 3) return 0;
   RlbmLayout L = make_layout(c->h_tab->c, nx, ny, 0, 0);
   return (size_t)L.total * elem_size(c->h_tab->c.precision);
 }
 
-extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n, const double* T,
-                                const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
-                                void* stream) {
-  if (!c || !lat) return fail(c, RLBM_EINVAL, "NULL context or lattice");
-  const RlbmConsts& k = c->h_tab->c;
+extern "C" size_t rlbm_population_bytes3(const rlbm_ctx* c, int nx, int ny, int nz) {
+  if (!c || nx <= 0 || ny <= 0 || nz <= 0 || c->h_tab->c.dim != 3) return 0;
+  RlbmLayout L = make_layout(c->h_tab->c, nx, ny, 0, 0, nz, 0);
+  return (size_t)L.total * elem_size(c->h_tab->c.precision);
+}
+
+// Everything about a lattice description that needs no device: sizes,
+// boundary rules, relaxation time, Landau options, and the layout's limits
+// (fewer than 2^31 stored elements, class byte offsets below 2^31).  Fills L
+// and the class offsets (offs[0, QMAX): own storage, [QMAX, 2 QMAX): pulled).
+// Returns nullptr, or the reason the description is rejected.
+static const char* check_lattice(const RlbmTable& t, const rlbm_lattice_desc* lat, RlbmLayout& L,
+                                 unsigned offs[2 * RLBM_QMAX]) {
+  const RlbmConsts& k = t.c;
+  if (!lat) return "NULL lattice description";
+  const int nz = k.dim == 3 ? lat->nz : 1;
   if (lat->nx <= 0 || lat->ny <= 0 || (k.dim == 1 && lat->ny != 1))
-    return fail(c, RLBM_EINVAL, "invalid lattice size (1D stencils need ny == 1)");
-  if ((long long)lat->nx * lat->ny > (1LL << 31) - 1) return fail(c, RLBM_EINVAL, "lattice too large");
-  if (lat->bc_x < 0 || lat->bc_x > 1 || lat->bc_y < 0 || lat->bc_y > 1) return fail(c, RLBM_EINVAL, "invalid bc");
+    return "invalid lattice size (1D stencils need ny == 1)";
+  if (k.dim == 3 ? lat->nz < 1 : (lat->nz < 0 || lat->nz > 1))
+    return "invalid nz (>= 1 for 3D stencils, 0 or 1 otherwise)";
+  if ((long long)lat->nx * lat->ny * nz > (1LL << 31) - 1) return "lattice too large";
+  if (lat->bc_x < 0 || lat->bc_x > 1 || lat->bc_y < 0 || lat->bc_y > 1) return "invalid bc";
+  if (k.dim == 3 && (lat->bc_z < 0 || lat->bc_z > 1)) return "invalid bc_z";
+  if (k.dim == 3 && lat->landau_method != RLBM_LANDAU_NEWTON) return "3D lattices solve the Landau frame by Newton";
   if (lat->tau_mode == RLBM_TAU_CONST) {
-    if (!(lat->tau > 0.5)) return fail(c, RLBM_EINVAL, "tau must exceed 1/2");
+    if (!(lat->tau > 0.5)) return "tau must exceed 1/2";
   } else if (lat->tau_mode == RLBM_TAU_ETA_OVER_S) {
     if (!(lat->eta_over_s > 0) || !(lat->T_R_GeV > 0) || !(lat->n_unit_fm3 > 0) || !(lat->dx_fm > 0))
-      return fail(c, RLBM_EINVAL, "eta/s mode needs eta_over_s, T_R_GeV, n_unit_fm3, dx_fm > 0");
+      return "eta/s mode needs eta_over_s, T_R_GeV, n_unit_fm3, dx_fm > 0";
   } else {
-    return fail(c, RLBM_EINVAL, "invalid tau mode");
+    return "invalid tau mode";
   }
+  if (lat->landau_maxit > 1000000) return "landau_maxit above 10^6";
+  if (lat->landau_method != RLBM_LANDAU_NEWTON && lat->landau_method != RLBM_LANDAU_FIXED_POINT)
+    return "invalid Landau method";
+  L = make_layout(k, lat->nx, lat->ny, lat->bc_x, lat->bc_y, nz, k.dim == 3 ? lat->bc_z : 0);
+  if (L.total >= (1LL << 31)) return "lattice too large (2^31 or more stored elements)";
+  const long long es = (long long)elem_size(k.precision);
+  const long long base = (long long)L.Sz * L.zs + (long long)L.Sy * L.rs + L.Sx;
+  for (int j = 0; j < RLBM_QMAX; ++j) {
+    const int jj = j < k.Q ? j : 0;  // padding classes read class 0's source
+    const long long own = base + jj * L.cs;
+    const long long src = own - (long long)t.nz[jj] * L.zs - (long long)t.ny[jj] * L.rs - t.nx[jj];
+    if (src < 0 || es * (own + L.Sz * L.zs + L.Sy * L.rs + L.Sx + kWave) >= (1LL << 31))
+      return "class offsets out of range";
+    offs[j] = (unsigned)(es * own);
+    offs[RLBM_QMAX + j] = (unsigned)(es * src);
+  }
+  return nullptr;
+}
+
+extern "C" int rlbm_check_lattice(const rlbm_stencil_desc* desc, const rlbm_lattice_desc* lat) {
+  if (!desc || !lat) return fail(nullptr, RLBM_EINVAL, "NULL stencil or lattice description");
+  std::unique_ptr<RlbmTable> t(new RlbmTable());
+  rlbm_stencil_info info;
+  char err[512] = {0};
+  const int rc = rlbm_build_table(desc, &info, t.get(), err, sizeof(err));
+  if (rc) return fail(nullptr, rc, "%s", err);
+  RlbmLayout L;
+  unsigned offs[2 * RLBM_QMAX];
+  if (const char* why = check_lattice(*t, lat, L, offs)) return fail(nullptr, RLBM_EINVAL, "%s", why);
+  return RLBM_OK;
+}
+
+// Device part of a field set-up: the class offsets of this lattice into the
+// context's table, and cleared health slots (a fill kernel, so that the
+// set-up records no memset node when a caller captures it in a graph).
+struct RlbmOffsetsArg {
+  unsigned v[2 * RLBM_QMAX];
+};
+
+__global__ void __launch_bounds__(kBlock) k_fields_setup(RlbmOffsetsArg o, RlbmTable* __restrict__ tab,
+                                                         RlbmSlot* __restrict__ slots, int nslots) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < 2 * RLBM_QMAX; j += kBlock) tab->offs[j] = o.v[j];
+  if (i < nslots) slots[i] = RlbmSlot{0u, 0u, 0ull};
+}
+
+static int init_fields_impl(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n, const double* T,
+                            const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
+                            void* stream) {
+  if (!c || !lat) return fail(c, RLBM_EINVAL, "NULL context or lattice");
+  const RlbmConsts& k = c->h_tab->c;
+  RlbmLayout L;
+  RlbmOffsetsArg offs;
+  if (const char* why = check_lattice(*c->h_tab, lat, L, offs.v)) return fail(c, RLBM_EINVAL, "%s", why);
   if (!n || !T || !ux || !uy || !popA || !popB || popA == popB)
     return fail(c, RLBM_EINVAL, "NULL field or population buffer");
-  size_t need = rlbm_population_bytes(c, lat->nx, lat->ny);
+  const size_t need = rlbm_population_bytes(c, lat->nx, lat->ny);
   if (pop_bytes < need) return fail(c, RLBM_EINVAL, "population buffer too small");
+  const int tiles_x = (lat->nx + kWave - 1) / kWave;
+  const long long ntiles = (long long)tiles_x * lat->ny;
   hipStream_t s = (hipStream_t)stream;
 
-  if (lat->landau_maxit > 1000000) return fail(c, RLBM_EINVAL, "landau_maxit above 10^6");
-  if (lat->landau_method != RLBM_LANDAU_NEWTON && lat->landau_method != RLBM_LANDAU_FIXED_POINT)
-    return fail(c, RLBM_EINVAL, "invalid Landau method");
   // from here on the context is being rebuilt: a failure leaves it without fields
   c->have_fields = false;
+  if (ntiles > c->nslots) {
+    if (c->d_slots) HIPCHECK(c, hipFree(c->d_slots));
+    c->d_slots = nullptr;
+    c->nslots = 0;
+    HIPCHECK(c, hipMalloc((void**)&c->d_slots, sizeof(RlbmSlot) * ntiles));
+    c->nslots = (int)ntiles;
+  }
+  RlbmSlot* slots = c->d_slots;
+  c->slots = slots;
   c->lat = *lat;
   c->warm = false;
   if (!(c->lat.landau_tol > 0)) c->lat.landau_tol = k.precision == RLBM_FP64 ? 1e-14 : 1e-10;
@@ -905,44 +1330,21 @@ extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const
   c->buf[0] = popA;
   c->buf[1] = popB;
   c->pop_bytes = pop_bytes;
-  c->L = make_layout(k, lat->nx, lat->ny, lat->bc_x, lat->bc_y);
-  if (c->L.total >= (1LL << 31)) return fail(c, RLBM_EINVAL, "lattice too large (2^31 or more stored elements)");
-  {
-    // byte offsets of each class's source from the lowest element a tile can
-    // reach (class 0 at (x0 - Sx, y - Sy)): [0, QMAX) in place (also the own
-    // storage the step writes), [QMAX, 2 QMAX) pulled
-    const long long es = k.precision == RLBM_FP64 ? 8 : k.precision == RLBM_FP32_DEV ? 4 : 2;
-    const long long base = (long long)c->L.Sy * c->L.rs + c->L.Sx;
-    std::vector<unsigned> offs(2 * RLBM_QMAX, 0);
-    for (int j = 0; j < RLBM_QMAX; ++j) {
-      const int jj = j < k.Q ? j : 0;  // padding classes read class 0's source
-      const long long own = base + jj * c->L.cs;
-      const long long src = own - (long long)c->h_tab->ny[jj] * c->L.rs - c->h_tab->nx[jj];
-      if (src < 0 || es * (own + c->L.Sy * c->L.rs + c->L.Sx + kWave) >= (1LL << 31))
-        return fail(c, RLBM_EINVAL, "class offsets out of range");
-      offs[j] = (unsigned)(es * own);
-      offs[RLBM_QMAX + j] = (unsigned)(es * src);
-    }
-    if (!c->d_offs) HIPCHECK(c, hipMalloc((void**)&c->d_offs, sizeof(unsigned) * 2 * RLBM_QMAX));
-    HIPCHECK(c, hipMemcpy(c->d_offs, offs.data(), sizeof(unsigned) * 2 * RLBM_QMAX, hipMemcpyHostToDevice));
-  }
+  c->L = L;
   c->cur = 0;
   c->shifted = 0;
   c->steps = 0;
-  c->tiles_x = (lat->nx + kWave - 1) / kWave;
-  c->ntiles = c->tiles_x * lat->ny;
-  if (c->ntiles != c->nslots) {
-    if (c->d_slots) HIPCHECK(c, hipFree(c->d_slots));
-    c->d_slots = nullptr;
-    HIPCHECK(c, hipMalloc((void**)&c->d_slots, sizeof(RlbmSlot) * c->ntiles));
-    c->nslots = c->ntiles;
-  }
-  HIPCHECK(c, hipMemsetAsync(c->d_slots, 0, sizeof(RlbmSlot) * c->nslots, s));
+  c->tiles_x = tiles_x;
+  c->ntiles = (int)ntiles;
   if (lat->tau_mode == RLBM_TAU_ETA_OVER_S) {
     const double TR = lat->T_R_GeV;
     c->tk1 = 1.5 * lat->eta_over_s * kHbarC * k.v0 / (lat->dx_fm * TR);
     c->tk2 = lat->n_unit_fm3 * M_PI * M_PI * kHbarC * kHbarC * kHbarC / (16.0 * TR * TR * TR);
   }
+  const long long nfill = std::max<long long>(ntiles, 1);
+  hipLaunchKernelGGL(k_fields_setup, dim3((unsigned)((nfill + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, offs,
+                     c->d_tab, slots, c->ntiles);
+  HIPCHECK(c, hipGetLastError());
   RlbmInitArgs ia;
   ia.dst = popA;
   ia.L = c->L;
@@ -958,6 +1360,12 @@ extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const
   HIPCHECK(c, hipGetLastError());
   c->have_fields = true;
   return RLBM_OK;
+}
+
+extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n, const double* T,
+                                const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
+                                void* stream) {
+  return init_fields_impl(c, lat, n, T, ux, uy, popA, popB, pop_bytes, stream);
 }
 
 extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
@@ -976,7 +1384,7 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   a.landau_maxit = c->lat.landau_maxit;
   a.landau_method = c->lat.landau_method;
   a.tab = c->d_tab;
-  a.slots = c->d_slots;
+  a.slots = c->slots;
   const bool g = c->guess != nullptr && c->h_tab->c.precision == RLBM_FP32_DEV;
   if (g) {
     a.mlp_frag = c->guess->frag;
@@ -994,12 +1402,14 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   a.fo_base = (unsigned)(es * ((long long)c->L.Sy * c->L.rs + c->L.Sx));
   a.fo_cs = (unsigned)(es * c->L.cs);
   const unsigned nwg = (unsigned)((c->ntiles + kStepBlock / kWave - 1) / (kStepBlock / kWave));
+  // class offsets of this lattice, in the context's device table
+  const unsigned* d_offs = (const unsigned*)((const char*)c->d_tab + offsetof(RlbmTable, offs));
   for (int i = 0; i < nsteps; ++i) {
     a.src = c->buf[c->cur];
     a.dst = c->buf[1 - c->cur];
     a.shift = c->shifted;
-    a.offs = c->d_offs + (c->shifted ? RLBM_QMAX : 0);
-    a.offs_st = c->d_offs;
+    a.offs = d_offs + (c->shifted ? RLBM_QMAX : 0);
+    a.offs_st = d_offs;
     a.warm = (c->warm && !g) ? c->d_warm : nullptr;
     a.warm_plane = (long long)c->L.nx * c->L.ny;
     a.fo_rs = c->shifted ? (int)(es * c->L.rs) : 0;
@@ -1044,8 +1454,8 @@ extern "C" int rlbm_get_health(rlbm_ctx* c, unsigned* flags, unsigned long long*
   if (!c->have_fields) return fail(c, RLBM_ESTATE, "no fields");
   hipStream_t s = (hipStream_t)stream;
   HIPCHECK(c, hipStreamSynchronize(s));
-  std::vector<RlbmSlot> h(c->nslots);
-  HIPCHECK(c, hipMemcpy(h.data(), c->d_slots, sizeof(RlbmSlot) * c->nslots, hipMemcpyDeviceToHost));
+  std::vector<RlbmSlot> h(c->ntiles);
+  HIPCHECK(c, hipMemcpy(h.data(), c->slots, sizeof(RlbmSlot) * c->ntiles, hipMemcpyDeviceToHost));
   unsigned f = 0, mx = 0;
   unsigned long long sm = 0;
   for (auto& x : h) {
@@ -1057,7 +1467,7 @@ extern "C" int rlbm_get_health(rlbm_ctx* c, unsigned* flags, unsigned long long*
   if (iter_sum) *iter_sum = sm;
   if (iter_max) *iter_max = mx;
   if (reset) {
-    HIPCHECK(c, hipMemsetAsync(c->d_slots, 0, sizeof(RlbmSlot) * c->nslots, s));
+    HIPCHECK(c, hipMemsetAsync(c->slots, 0, sizeof(RlbmSlot) * c->ntiles, s));
     HIPCHECK(c, hipStreamSynchronize(s));
   }
   if (f & RLBM_H_FATAL) return fail(c, RLBM_ENUMERIC, "fatal health flag raised (0x%s)", "see flags");
@@ -1157,13 +1567,16 @@ extern "C" int rlbm_landau_guess_fields(rlbm_ctx* c, float* out, void* stream) {
 //
 // Many independent 1D problems (float32 deviation storage, outflow ends, tau
 // from eta/s), each with its own stencil, advanced for many steps in ONE
-// launch: one workgroup owns one problem and loops over its sites; a
-// workgroup barrier separates the steps (the ping-pong buffers of a problem
-// are touched by its workgroup only).
+// cooperative launch that spans the whole chip: the sites of every problem
+// are cut into tiles of 64 consecutive sites (one wave each, so a wave never
+// straddles two problems and reads its stencil's rows through the scalar
+// cache), the tiles are dealt round-robin to the waves of the grid, and a
+// grid-wide barrier separates the steps.  Every wave takes part in every
+// barrier, tiles or not, so the launch always drains.
 
 namespace rlbm {
 
-constexpr int kBatchBlock = 1024;
+constexpr int kBatchBlock = 256;
 constexpr int kBatchQ = 24;  // classes of a 1D stencil
 
 struct RlbmBatchProblem {
@@ -1175,6 +1588,11 @@ struct RlbmBatchProblem {
   double tk1, tk2;     // tau = 1/2 + tk1 (4 - ln(tk2 n / T^3)) / T
 };
 
+struct RlbmBatchTile {
+  int prob;  // problem index
+  int x0;    // first site of the tile
+};
+
 struct RlbmBatchArgs {
   const void* src;
   void* dst;
@@ -1184,12 +1602,17 @@ struct RlbmBatchArgs {
   float* samples;       // [nsamples][total_sites][12] or NULL
   long long total_sites;
   const RlbmBatchProblem* probs;
+  const RlbmBatchTile* tiles;
+  int ntiles;
   const RlbmTable* const* tables;
   double landau_tol;
   int landau_maxit;
-  RlbmSlot* slots;      // one per problem
+  RlbmSlot* slots;      // one per wave of the grid
 };
 
+// One site of one problem: pull, moments (float32 rows plus their rounding
+// remainders), Landau frame, EOS, projections, equilibrium and relaxation,
+// store (and the outflow ghosts at the ends).
 __device__ __forceinline__ void batch_site(const RlbmBatchArgs& a, const RlbmBatchProblem& pr, TabPtr tb,
                                            const float* __restrict__ src, float* __restrict__ dst, int x, int shift,
                                            float* __restrict__ sample, unsigned& flags, unsigned& iters) {
@@ -1199,16 +1622,20 @@ __device__ __forceinline__ void batch_site(const RlbmBatchArgs& a, const RlbmBat
   for (int j = 0; j < kBatchQ; ++j)
     f[j] = j < Q ? src[pr.base + (long long)j * pr.W + x + pr.S - (shift ? tb->nx[j] : 0)] : 0.0f;
   float m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  float ml[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int j = 0; j < kBatchQ; ++j) {
     if (j < Q) {
 #pragma unroll
-      for (int k = 0; k < 9; ++k) m[k] = fmaf(f[j], tb->rowmf[j][k], m[k]);
+      for (int k = 0; k < 9; ++k) {
+        m[k] = fmaf(f[j], tb->rowmf[j][k], m[k]);
+        ml[k] = fmaf(f[j], tb->rowmf_lo[j][k], ml[k]);
+      }
     }
   }
   double md[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) md[k] = tb->c.ref_mom[k] + (double)m[k];
+  for (int k = 0; k < 9; ++k) md[k] = tb->c.ref_mom[k] + ((double)m[k] + (double)ml[k]);
   Macro mac = macroscopic(tb, md[0], md[1], md[2], md[3], md[4], md[5], md[6], md[7], md[8], a.landau_tol,
                           a.landau_maxit, RLBM_LANDAU_NEWTON);
   flags |= mac.flags;
@@ -1223,7 +1650,7 @@ __device__ __forceinline__ void batch_site(const RlbmBatchArgs& a, const RlbmBat
   const double tau = tau_eta_over_s(pr.tk1, pr.tk2, mac.n, mac.T);
   double b[RLBM_NB];
   projections(tb, mac.T, mac.R, mac.gamma, mac.gamma * mac.ux, mac.gamma * mac.uy, b);
-  const double w0 = mac.gamma / tau;
+  const double w0 = div_nr(mac.gamma, tau);
   const float W0 = (float)w0, WX = (float)(-w0 * tb->c.v0 * mac.ux), WY = (float)(-w0 * tb->c.v0 * mac.uy);
   float nb[RLBM_NB];
 #pragma unroll
@@ -1232,11 +1659,15 @@ __device__ __forceinline__ void batch_site(const RlbmBatchArgs& a, const RlbmBat
   for (int j = 0; j < kBatchQ; ++j) {
     if (j < Q) {
       const auto* r = tb->rowf[j];
-      float feq = nb[0] * r[0];
+      const auto* rl = tb->rowf_lo[j];
+      float feq = nb[0] * r[0], feql = nb[0] * rl[0];
 #pragma unroll
-      for (int k = 1; k < RLBM_NB; ++k) feq = fmaf(nb[k], r[k], feq);
+      for (int k = 1; k < RLBM_NB; ++k) {
+        feq = fmaf(nb[k], r[k], feq);
+        feql = fmaf(nb[k], rl[k], feql);
+      }
       const float om = fmaf(WY, r[RLBM_R_NY], fmaf(WX, r[RLBM_R_NX], W0));
-      const float out = fmaf(-om, f[j] - feq, f[j]);
+      const float out = fmaf(-om, (f[j] - feq) - feql, f[j]);
       float* q = dst + pr.base + (long long)j * pr.W + pr.S;
       q[x] = out;
       // outflow ghosts: the end sites stand for every site beyond them
@@ -1249,52 +1680,45 @@ __device__ __forceinline__ void batch_site(const RlbmBatchArgs& a, const RlbmBat
 }
 
 __global__ void __launch_bounds__(kBatchBlock) k_batch(RlbmBatchArgs a) {
-  const RlbmBatchProblem pr = a.probs[blockIdx.x];
-  const TabPtr tb = as_tab(a.tables[pr.table]);
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  const int lane = (int)threadIdx.x & (kWave - 1);
+  const int wave = (int)blockIdx.x * (kBatchBlock / kWave) + (int)(threadIdx.x >> 6);
+  const int nwaves = (int)gridDim.x * (kBatchBlock / kWave);
   const float* src = (const float*)a.src;
   float* dst = (float*)a.dst;
   int shift = a.shift;
   unsigned flags = 0, imax = 0, isum = 0;
   for (int t = 0; t < a.nsteps; ++t) {
     const bool sampling = a.samples != nullptr && (t % a.sample_every) == 0;
-    float* srow = sampling ? a.samples + ((long long)(t / a.sample_every) * a.total_sites + pr.site_off) * 12 : nullptr;
-    for (int x0 = 0; x0 < pr.L; x0 += kBatchBlock) {
-      const int x = x0 + (int)threadIdx.x;
+    for (int tile = wave; tile < a.ntiles; tile += nwaves) {
+      const RlbmBatchTile tl = a.tiles[tile];
+      const int prob = __builtin_amdgcn_readfirstlane(tl.prob);
+      const RlbmBatchProblem pr = a.probs[prob];
+      const TabPtr tb = as_tab(a.tables[pr.table]);
+      const int x = __builtin_amdgcn_readfirstlane(tl.x0) + lane;
       if (x < pr.L) {
+        float* srow = sampling ? a.samples + ((long long)(t / a.sample_every) * a.total_sites + pr.site_off + x) * 12
+                               : nullptr;
         unsigned it = 0;
-        batch_site(a, pr, tb, src, dst, x, shift, srow ? srow + (long long)x * 12 : nullptr, flags, it);
+        batch_site(a, pr, tb, src, dst, x, shift, srow, flags, it);
         imax = max(imax, it);
         isum += it;
       }
     }
-    __syncthreads();  // every site of this step is written before the next step reads it
+    // every site of this step is written before any wave reads it in the
+    // next step: device-scope fences around the grid barrier release this
+    // step's stores and keep another XCD's L2 from serving stale lines
+    __threadfence();
+    grid.sync();
+    __threadfence();
     const float* tmp = src;
     src = dst;
     dst = (float*)tmp;
     shift = 1;
   }
-  // per-problem statistics (thread-level values reduced over the block)
-  __shared__ unsigned s_f[kBatchBlock / 64], s_m[kBatchBlock / 64], s_s[kBatchBlock / 64];
-  for (int off = 32; off > 0; off >>= 1) {
-    flags |= __shfl_xor(flags, off);
-    imax = max(imax, (unsigned)__shfl_xor(imax, off));
-    isum += __shfl_xor(isum, off);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    s_f[threadIdx.x >> 6] = flags;
-    s_m[threadIdx.x >> 6] = imax;
-    s_s[threadIdx.x >> 6] = isum;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    RlbmSlot s = a.slots[blockIdx.x];
-    for (int i = 0; i < kBatchBlock / 64; ++i) {
-      s.flags |= s_f[i];
-      s.iter_max = max(s.iter_max, s_m[i]);
-      s.iter_sum += s_s[i];
-    }
-    a.slots[blockIdx.x] = s;
-  }
+  // per-wave statistics into the wave's own slot
+  wave_stats(a.slots, wave, flags, imax, isum);
 }
 
 // f = f^eq(n, T, u) of every problem (fields concatenated over the problems)
@@ -1354,7 +1778,11 @@ struct rlbm_batch {
   int cur = 0, shifted = 0;
   long long steps = 0;
   bool have_fields = false;
-  RlbmSlot* d_slots = nullptr;
+  RlbmSlot* d_slots = nullptr;      // one per wave of the cooperative grid
+  RlbmBatchTile* d_tiles = nullptr;  // 64-site tiles of every problem
+  int ntiles = 0;
+  int workgroups = 0;                // cooperative grid (kBatchBlock threads each)
+  int resident_limit = 0;            // workgroups the device holds at once for k_batch
   double landau_tol = 1e-10;
   int landau_maxit = 200;
 };
@@ -1413,18 +1841,46 @@ extern "C" int rlbm_batch_create(rlbm_batch** out, int nstencils, rlbm_ctx* cons
   }
   b->total_sites = sites;
   b->total_elems = elems;
+  // 64-site tiles of every problem, dealt round-robin to the grid's waves
+  std::vector<RlbmBatchTile> tiles;
+  for (int p = 0; p < nprob; ++p)
+    for (int x0 = 0; x0 < b->h_probs[p].L; x0 += kWave) tiles.push_back(RlbmBatchTile{p, x0});
+  b->ntiles = (int)tiles.size();
+  // the cooperative grid: one wave per tile, no more workgroups than the
+  // device holds at once (a cooperative launch needs them all resident)
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch, kBatchBlock, 0) != hipSuccess || per_cu < 1) {
+    delete b;
+    return bfail("rlbm_batch_create: occupancy query failed");
+  }
+  b->resident_limit = per_cu * cus;
+  const int want = (b->ntiles + kBatchBlock / kWave - 1) / (kBatchBlock / kWave);
+  b->workgroups = std::max(1, std::min(want, b->resident_limit));
+  const int nwaves = b->workgroups * (kBatchBlock / kWave);
   std::vector<const RlbmTable*> tabs(nstencils);
   for (int s = 0; s < nstencils; ++s) tabs[s] = stencils[s]->d_tab;
   if (hipMalloc((void**)&b->d_probs, sizeof(RlbmBatchProblem) * nprob) != hipSuccess ||
       hipMalloc((void**)&b->d_tables, sizeof(RlbmTable*) * nstencils) != hipSuccess ||
-      hipMalloc((void**)&b->d_slots, sizeof(RlbmSlot) * nprob) != hipSuccess) {
+      hipMalloc((void**)&b->d_slots, sizeof(RlbmSlot) * nwaves) != hipSuccess ||
+      hipMalloc((void**)&b->d_tiles, sizeof(RlbmBatchTile) * b->ntiles) != hipSuccess) {
     rlbm_batch_destroy(b);
     return bfail("rlbm_batch_create: device allocation failed");
   }
   BHIP(hipMemcpy(b->d_probs, b->h_probs.data(), sizeof(RlbmBatchProblem) * nprob, hipMemcpyHostToDevice));
   BHIP(hipMemcpy(b->d_tables, tabs.data(), sizeof(RlbmTable*) * nstencils, hipMemcpyHostToDevice));
-  BHIP(hipMemset(b->d_slots, 0, sizeof(RlbmSlot) * nprob));
+  BHIP(hipMemcpy(b->d_tiles, tiles.data(), sizeof(RlbmBatchTile) * b->ntiles, hipMemcpyHostToDevice));
+  BHIP(hipMemset(b->d_slots, 0, sizeof(RlbmSlot) * nwaves));
   *out = b;
+  return RLBM_OK;
+}
+
+extern "C" int rlbm_batch_occupancy(const rlbm_batch* b, int* workgroups, int* resident_limit, int* tiles) {
+  if (!b) return bfail("rlbm_batch_occupancy: NULL");
+  if (workgroups) *workgroups = b->workgroups;
+  if (resident_limit) *resident_limit = b->resident_limit;
+  if (tiles) *tiles = b->ntiles;
   return RLBM_OK;
 }
 
@@ -1434,6 +1890,7 @@ extern "C" int rlbm_batch_destroy(rlbm_batch* b) {
   if (b->d_probs) (void)hipFree(b->d_probs);
   if (b->d_tables) (void)hipFree((void*)b->d_tables);
   if (b->d_slots) (void)hipFree(b->d_slots);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
   delete b;
   return RLBM_OK;
 }
@@ -1454,7 +1911,7 @@ extern "C" int rlbm_batch_init(rlbm_batch* b, const double* n, const double* T, 
   b->shifted = 0;
   b->steps = 0;
   hipStream_t s = (hipStream_t)stream;
-  BHIP(hipMemsetAsync(b->d_slots, 0, sizeof(RlbmSlot) * b->nprob, s));
+  BHIP(hipMemsetAsync(b->d_slots, 0, sizeof(RlbmSlot) * b->workgroups * (kBatchBlock / kWave), s));
   hipLaunchKernelGGL(k_batch_init, dim3(b->nprob), dim3(256), 0, s, b->d_probs, b->d_tables, n, T, ux,
                      (float*)popA);
   BHIP(hipGetLastError());
@@ -1479,7 +1936,11 @@ extern "C" int rlbm_batch_step_persistent(rlbm_batch* b, int nsteps, int sample_
   a.landau_tol = b->landau_tol;
   a.landau_maxit = b->landau_maxit;
   a.slots = b->d_slots;
-  hipLaunchKernelGGL(k_batch, dim3(b->nprob), dim3(kBatchBlock), 0, (hipStream_t)stream, a);
+  a.tiles = b->d_tiles;
+  a.ntiles = b->ntiles;
+  void* kargs[] = {&a};
+  BHIP(hipLaunchCooperativeKernel((const void*)k_batch, dim3(b->workgroups), dim3(kBatchBlock), kargs, 0,
+                                  (hipStream_t)stream));
   BHIP(hipGetLastError());
   if (nsteps % 2) b->cur ^= 1;
   b->shifted = 1;
@@ -1500,8 +1961,9 @@ extern "C" int rlbm_batch_get_health(rlbm_batch* b, unsigned* flags, unsigned lo
                                      unsigned* iter_max, void* stream) {
   if (!b) return bfail("rlbm_batch_get_health: NULL");
   BHIP(hipStreamSynchronize((hipStream_t)stream));
-  std::vector<RlbmSlot> h(b->nprob);
-  BHIP(hipMemcpy(h.data(), b->d_slots, sizeof(RlbmSlot) * b->nprob, hipMemcpyDeviceToHost));
+  const int nslots = b->workgroups * (kBatchBlock / kWave);
+  std::vector<RlbmSlot> h(nslots);
+  BHIP(hipMemcpy(h.data(), b->d_slots, sizeof(RlbmSlot) * nslots, hipMemcpyDeviceToHost));
   unsigned f = 0, mx = 0;
   unsigned long long sm = 0;
   for (auto& x : h) {

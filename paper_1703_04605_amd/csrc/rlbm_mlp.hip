@@ -6,7 +6,7 @@
 // Training kernels (this file) work on float32 activations; the in-step
 // inference (rlbm_lib.hip) uses matrix-core products on bfloat16 operands,
 // with the weights re-packed here into the per-lane fragment order of the
-// 32x32x8 bf16 matrix instruction.
+// 32x32x16 bf16 matrix instruction.
 #include <hip/hip_runtime.h>
 #include <stdio.h>
 #include <string.h>

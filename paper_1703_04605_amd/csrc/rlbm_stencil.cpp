@@ -238,9 +238,9 @@ static ld k1k2_ld(ld z) { return besselk_scaled_ld(1, z) / besselk_scaled_ld(2, 
 
 int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTable* tab, char* err,
                      size_t errlen) {
-  if (!d || !d->group_base || d->n_groups != 6 || !(d->zeta > 0) || (d->dim != 1 && d->dim != 2) ||
+  if (!d || !d->group_base || d->n_groups != 6 || !(d->zeta > 0) || d->dim < 1 || d->dim > 3 ||
       d->precision < RLBM_FP64 || d->precision > RLBM_FP16_DEV) {
-    set_err(err, errlen, "invalid stencil description (second order needs 6 groups, zeta > 0, dim 1|2)");
+    set_err(err, errlen, "invalid stencil description (second order needs 6 groups, zeta > 0, dim 1|2|3)");
     return RLBM_EINVAL;
   }
   for (int i = 0; i < 3 * d->n_groups; ++i)
@@ -305,11 +305,49 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
         break;
       }
     }
-    for (int it = 0; it < 100; ++it) {
-      ld mid = 0.5L * (l_in + l_out);
-      if (st.min_weight(mid) > 0) l_in = mid; else l_out = mid;
-      mid = 0.5L * (r_in + r_out);
-      if (st.min_weight(mid) > 0) r_in = mid; else r_out = mid;
+    auto bisect = [&st](ld& in, ld& out) {
+      for (int it = 0; it < 100; ++it) {
+        const ld mid = 0.5L * (in + out);
+        if (st.min_weight(mid) > 0) in = mid; else out = mid;
+      }
+    };
+    bisect(l_in, l_out);
+    bisect(r_in, r_out);
+    // A doubled step can jump over a run of negative weights into another
+    // positive run; the window must be the run that holds `best`.  Sample it:
+    // if any interior point is not positive, walk out from `best` at the
+    // finest spacing instead (bounded), and bisect from there.
+    auto connected = [&st](ld x0, ld x1) {
+      for (int i = 1; i < 64; ++i)
+        if (!(st.min_weight(x0 + (x1 - x0) * i / 64) > 0)) return false;
+      return true;
+    };
+    if (!connected(l_in, best) || !connected(best, r_in)) {
+      // (a walk that ends without leaving the run keeps its last point as the
+      // edge: out == in leaves nothing to bisect)
+      l_in = best, r_in = best;
+      l_out = lo, r_out = hi;
+      bool l_found = false, r_found = false;
+      for (int i = 1; i <= 100000 && best - i * step0 > lo; ++i) {
+        if (st.min_weight(best - i * step0) > 0) {
+          l_in = best - i * step0;
+        } else {
+          l_out = best - i * step0;
+          l_found = true;
+          break;
+        }
+      }
+      for (int i = 1; i <= 100000 && best + i * step0 < hi; ++i) {
+        if (st.min_weight(best + i * step0) > 0) {
+          r_in = best + i * step0;
+        } else {
+          r_out = best + i * step0;
+          r_found = true;
+          break;
+        }
+      }
+      if (l_found) bisect(l_in, l_out);
+      if (r_found) bisect(r_in, r_out);
     }
     wlo = l_in;
     whi = r_in;
@@ -351,11 +389,13 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
     return RLBM_ENOSTENCIL;
   }
 
-  // classes: (group, nx, ny) in 2D, (group, nx) in 1D
-  std::map<std::tuple<int, int, int>, int> key2class;
+  // classes: (group, nx, ny) in 2D, (group, nx) in 1D; in 3D every
+  // population is its own class
+  std::map<std::tuple<int, int, int, int>, int> key2class;
   std::vector<std::vector<int>> members;
   for (size_t i = 0; i < pops.size(); ++i) {
-    auto key = std::make_tuple(pops[i].g, pops[i].n[0], d->dim == 2 ? pops[i].n[1] : 0);
+    auto key = std::make_tuple(pops[i].g, pops[i].n[0], d->dim >= 2 ? pops[i].n[1] : 0,
+                               d->dim == 3 ? pops[i].n[2] : 0);
     auto it = key2class.find(key);
     if (it == key2class.end()) {
       key2class[key] = (int)members.size();
@@ -369,12 +409,13 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
     set_err(err, errlen, "stencil has more population classes than the library supports");
     return RLBM_EINVAL;
   }
-  int max_shift = 0, sx_max = 0, sy_max = 0;
+  int max_shift = 0, sx_max = 0, sy_max = 0, sz_max = 0;
   for (auto& p : pops) {
     sx_max = std::max(sx_max, abs(p.n[0]));
-    if (d->dim == 2) sy_max = std::max(sy_max, abs(p.n[1]));
+    if (d->dim >= 2) sy_max = std::max(sy_max, abs(p.n[1]));
+    if (d->dim == 3) sz_max = std::max(sz_max, abs(p.n[2]));
   }
-  max_shift = std::max(sx_max, sy_max);
+  max_shift = std::max(sx_max, std::max(sy_max, sz_max));
   if (max_shift > 16) {
     set_err(err, errlen, "displacements above 16 lattice sites are not supported");
     return RLBM_EINVAL;
@@ -401,6 +442,7 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
   c.max_shift = max_shift;
   c.sx_max = sx_max;
   c.sy_max = sy_max;
+  c.sz_max = sz_max;
   c.zeta = d->zeta;
   c.inv_zeta = (double)(1.0L / (ld)d->zeta);
   c.v0 = (double)v0;
@@ -419,9 +461,11 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
   for (int j = 0; j < Q; ++j) {
     const Pop& p0 = pops[members[j][0]];
     tab->nx[j] = p0.n[0];
-    tab->ny[j] = d->dim == 2 ? p0.n[1] : 0;
+    tab->ny[j] = d->dim >= 2 ? p0.n[1] : 0;
+    tab->nz[j] = d->dim == 3 ? p0.n[2] : 0;
     const auto& m0 = mom[members[j][0]];
-    pj[j] = {m0[0], m0[1], d->dim == 2 ? m0[2] : 0.0L};
+    pj[j] = {m0[0], m0[1], d->dim >= 2 ? m0[2] : 0.0L};
+    tab->pz[j] = d->dim == 3 ? (double)m0[3] : 0.0;
     for (int k = 0; k < RLBM_NB; ++k) {
       ld s = 0;
       for (int i : members[j]) s += w[pops[i].g] * Jall[i][kInPlane[k]];
@@ -469,11 +513,13 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
     // divided by f^ref_j and moment monomials multiplied by it.
     const bool ratio = d->precision == RLBM_FP16_DEV;
     const ld fref = ratio ? (ld)tab->scale[j] : 1.0L;
+    const bool split = d->precision == RLBM_FP32_DEV;
     for (int k = 0; k < RLBM_NB; ++k) {
       tab->M[k][j] = (double)Mld[j][k];
       tab->Mf[k][j] = (float)Mld[j][k];
       tab->rowf[j][k] = (float)(Mld[j][k] / fref);
       tab->rowd[j][k] = (double)Mld[j][k];
+      tab->rowf_lo[j][k] = split ? (float)(Mld[j][k] - (ld)tab->rowf[j][k]) : 0.0f;
     }
     tab->rowf[j][RLBM_R_NX] = tab->fnx[j];
     tab->rowf[j][RLBM_R_NY] = tab->fny[j];
@@ -486,8 +532,55 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
     for (int a = 0; a < 9; ++a) {
       tab->rowmf[j][a] = (float)(mono[a] * fref);
       tab->rowmd[j][a] = (double)mono[a];
+      tab->rowmf_lo[j][a] = split ? (float)(mono[a] - (ld)tab->rowmf[j][a]) : 0.0f;
     }
     tab->rowmf[j][RLBM_RM_SCALE] = tab->scale[j];
+  }
+  if (d->dim == 3) {
+    // rows of the 3D step kernel: every population is a class of one
+    ld rb[RLBM_NB3] = {};
+    rb[0] = b[0];
+    rb[1] = b[1];
+    rb[5] = b[4];
+    ld ref3[RLBM_NB3] = {};
+    for (int k = 0; k < RLBM_NB3; ++k) c.nb_ref3[k] = (double)(nref * rb[k]);
+    const bool ratio = d->precision == RLBM_FP16_DEV;
+    const bool split = d->precision == RLBM_FP32_DEV;
+    for (int j = 0; j < Q; ++j) {
+      const int i = members[j][0];
+      const ld wi = w[pops[i].g];
+      ld M3[RLBM_NB3];
+      ld fr = 0;
+      for (int k = 0; k < RLBM_NB3; ++k) {
+        M3[k] = wi * Jall[i][k];
+        fr += nref * rb[k] * M3[k];
+      }
+      const ld p0 = mom[i][0], px = mom[i][1], py = mom[i][2], pz = mom[i][3];
+      const ld mono[RLBM_NB3] = {p0,      px,      py,      pz,      p0 * p0, p0 * px, p0 * py,
+                                 p0 * pz, px * px, px * py, px * pz, py * py, py * pz, pz * pz};
+      for (int a = 0; a < RLBM_NB3; ++a) ref3[a] += fr * mono[a];
+      const ld fref = ratio ? (ld)(float)fr : 1.0L;
+      for (int k = 0; k < RLBM_NB3; ++k) {
+        tab->row3d[j][k] = (double)M3[k];
+        tab->row3f[j][k] = (float)(M3[k] / fref);
+        tab->row3f_lo[j][k] = split ? (float)(M3[k] - (ld)tab->row3f[j][k]) : 0.0f;
+      }
+      const int nv[3] = {pops[i].n[0], pops[i].n[1], pops[i].n[2]};
+      for (int a = 0; a < 3; ++a) {
+        tab->row3d[j][RLBM_R3_NX + a] = (double)nv[a];
+        tab->row3f[j][RLBM_R3_NX + a] = (float)nv[a];
+      }
+      tab->row3f[j][RLBM_R3_INVSCALE] = (float)(1.0L / (ld)(float)fr);
+      for (int a = 0; a < RLBM_NB3; ++a) {
+        tab->rowm3d[j][a] = (double)mono[a];
+        tab->rowm3f[j][a] = (float)(mono[a] * fref);
+        tab->rowm3f_lo[j][a] = split ? (float)(mono[a] - (ld)tab->rowm3f[j][a]) : 0.0f;
+      }
+      tab->rowm3f[j][RLBM_RM3_SCALE] = (float)fr;
+      tab->scale[j] = (float)fr;
+      tab->inv_scale[j] = (float)(1.0L / (ld)(float)fr);
+    }
+    for (int a = 0; a < RLBM_NB3; ++a) c.ref_mom3[a] = (double)ref3[a];
   }
   return RLBM_OK;
 }
@@ -510,6 +603,8 @@ uint64_t rlbm_table_fingerprint(const RlbmTable* t) {
   for (int j = 0; j < Q; ++j) {
     mix(t->rowmf[j], sizeof(float) * 9);
     mix(t->rowf[j], sizeof(float) * RLBM_NB);
+    mix(t->rowmf_lo[j], sizeof(float) * 9);
+    mix(t->rowf_lo[j], sizeof(float) * RLBM_NB);
   }
   // float64 constants compiled into the generated kernels
   const RlbmConsts& c = t->c;

@@ -15,7 +15,8 @@ void rlbm_set_global_error(const char* msg);
 
 // 64-bit FNV-1a fingerprint of the parts of a class table that the fixed-
 // stencil kernels compile in (class count, dimension, precision, class
-// displacements, float moment and equilibrium rows, float64 constants).
+// displacements, float moment and equilibrium rows and their rounding
+// remainders, float64 constants).
 uint64_t rlbm_table_fingerprint(const RlbmTable* t);
 
 // Chebyshev pieces of the inverse equation of state T(u)/u for mbar = zeta

@@ -22,6 +22,17 @@ enum { RLBM_R_NX = 10, RLBM_R_NY = 11, RLBM_R_INVSCALE = 12 };
 #define RLBM_ROWMD 10
 #define RLBM_RM_SCALE 9
 
+// 3D lattices: all 14 second-order polynomials (Appendix A order 0, 1_0,
+// 1_x, 1_y, 1_z, 2_00, 2_0x, 2_0y, 2_0z, 2_xx, 2_yy, 2_xz, 2_yz, 2_xy);
+// equilibrium rows [M_j0 .. M_j13, n_x, n_y, n_z, 1/scale], moment rows
+// [p0, px, py, pz, p0p0, p0px, p0py, p0pz, pxpx, pxpy, pxpz, pypy, pypz,
+// pzpz, scale, 0]
+#define RLBM_NB3 14
+#define RLBM_ROW3 18
+#define RLBM_ROWM3 16
+enum { RLBM_R3_NX = 14, RLBM_R3_NY = 15, RLBM_R3_NZ = 16, RLBM_R3_INVSCALE = 17 };
+#define RLBM_RM3_SCALE 14
+
 #define RLBM_LANDAU_NEWTON 0      // Newton on det(lambda I - T eta) from lambda = T^00
 #define RLBM_LANDAU_FIXED_POINT 1 // eps = T^00 - T^0i u_i, u_i = (T^0i - T^ij u_j)/eps
 
@@ -33,10 +44,10 @@ enum { RLBM_R_NX = 10, RLBM_R_NY = 11, RLBM_R_INVSCALE = 12 };
 
 struct RlbmConsts {
   int Q;          // population classes (planes)
-  int dim;        // 1 or 2
+  int dim;        // 1, 2 or 3
   int precision;  // RLBM_FP64 / RLBM_FP32_DEV / RLBM_FP16_DEV
   int max_shift;
-  int sx_max, sy_max;  // max |n_x|, max |n_y| over the classes
+  int sx_max, sy_max, sz_max;  // max |n_x|, max |n_y|, max |n_z| over the classes
   double zeta;    // mbar = m / T_R
   double inv_zeta;
   double v0;
@@ -51,6 +62,8 @@ struct RlbmConsts {
   double n_ref, T_ref;
   double nb_ref[RLBM_NB];  // n_ref * b_k(rest, T_ref)
   double ref_mom[9];       // sum_j f^ref_j (p0, px, py, p0p0, p0px, p0py, pxpx, pxpy, pypy)
+  double nb_ref3[RLBM_NB3];  // 3D: n_ref * b_k(rest, T_ref) for all 14 polynomials
+  double ref_mom3[RLBM_NB3]; // 3D: sum_j f^ref_j times the 14 monomials of the 3D moment rows
 };
 
 struct RlbmTable {
@@ -73,6 +86,29 @@ struct RlbmTable {
   // mj-discrete-second-moment (and the FP16 scale), one wide scalar load each.
   float rowmf[RLBM_QMAX][RLBM_ROWMF] __attribute__((aligned(64)));
   double rowmd[RLBM_QMAX][RLBM_ROWMD] __attribute__((aligned(64)));
+  // float32 storage: the rounding remainders of the float rows (row value -
+  // float row, rounded to float), so that hi + lo carries each coefficient to
+  // about 2^-48.  A float row alone biases every step's moments and
+  // equilibrium by its rounding (about 2^-25 relative), which accumulates in
+  // the conserved quantities over long runs.  Zero in the other modes.
+  float rowf_lo[RLBM_QMAX][RLBM_ROWF] __attribute__((aligned(64)));
+  float rowmf_lo[RLBM_QMAX][RLBM_ROWMF] __attribute__((aligned(64)));
+  // 3D lattices (every population its own class): z displacement, p^z, and
+  // the rows of the 3D step kernel (layouts above); float rows carry the
+  // FP16 scale as in 2D, and the float32 remainders as in 2D.
+  int nz[RLBM_QMAX];
+  double pz[RLBM_QMAX];
+  double row3d[RLBM_QMAX][RLBM_ROW3] __attribute__((aligned(64)));
+  float row3f[RLBM_QMAX][RLBM_ROW3] __attribute__((aligned(64)));
+  float row3f_lo[RLBM_QMAX][RLBM_ROW3] __attribute__((aligned(64)));
+  double rowm3d[RLBM_QMAX][RLBM_ROWM3] __attribute__((aligned(64)));
+  float rowm3f[RLBM_QMAX][RLBM_ROWM3] __attribute__((aligned(64)));
+  float rowm3f_lo[RLBM_QMAX][RLBM_ROWM3] __attribute__((aligned(64)));
+  // Per-lattice byte offsets of every class from the lowest element a tile
+  // can reach (class 0 at (x0 - Sx, y - Sy)): [0, QMAX) in place (the own
+  // storage the step writes), [QMAX, 2 QMAX) pulled.  Written on the device
+  // by rlbm_init_fields for the lattice in use.
+  unsigned offs[2 * RLBM_QMAX] __attribute__((aligned(64)));
 };
 
 // Per-block health / statistics slot, accumulated by the step kernel.
@@ -89,14 +125,17 @@ struct RlbmSlot {
 // pulls and stores stay within a few pages.  The ghost columns [-Sx, 0),
 // [nx, nx+Sx) and rows [-Sy, 0), [ny, ny+Sy) hold copies written by the owner
 // sites under the boundary rule, so pulls f_j(x - n_j) need no wrap or clamp.
+// 3D lattices stack (nz + 2 GZ) such planes of storage rows, zs elements
+// apart (2D: nz = 1, GZ = Sz = 0).
 struct RlbmLayout {
   long long cs;     // elements between classes at one site (W)
   long long rs;     // elements between storage rows (Q W)
+  long long zs;     // elements between storage planes ((ny + 2 GY) rs)
   long long total;  // elements of the whole buffer (padded)
-  int W, GX, GY;
-  int nx, ny;
-  int Sx, Sy;       // ghost widths actually used (max shifts)
-  int bc_x, bc_y;
+  int W, GX, GY, GZ;
+  int nx, ny, nz;
+  int Sx, Sy, Sz;   // ghost widths actually used (max shifts)
+  int bc_x, bc_y, bc_z;
 };
 
 struct RlbmStepArgs {

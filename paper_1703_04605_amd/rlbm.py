@@ -34,7 +34,8 @@ EXPORTS = ["rlbm_init_stencil", "rlbm_solve_stencil", "rlbm_class_table", "rlbm_
            "rlbm_set_warm_start",
            "rlbm_landau_guess_fields", "rlbm_batch_create", "rlbm_batch_destroy", "rlbm_batch_population_bytes",
            "rlbm_batch_sites", "rlbm_batch_init", "rlbm_batch_step_persistent", "rlbm_batch_moments",
-           "rlbm_batch_get_health", "rlbm_set_step_variant", "rlbm_step_kernel"]
+           "rlbm_batch_get_health", "rlbm_set_step_variant", "rlbm_step_kernel", "rlbm_check_lattice",
+           "rlbm_batch_occupancy"]
 
 STEP_AUTO, STEP_TABLE, STEP_FIXED = 0, 1, 2
 
@@ -63,7 +64,8 @@ class LatticeDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("bc_x", ctypes.c_int), ("bc_y", ctypes.c_int),
                 ("tau_mode", ctypes.c_int), ("tau", ctypes.c_double), ("eta_over_s", ctypes.c_double),
                 ("T_R_GeV", ctypes.c_double), ("n_unit_fm3", ctypes.c_double), ("dx_fm", ctypes.c_double),
-                ("landau_tol", ctypes.c_double), ("landau_maxit", ctypes.c_int), ("landau_method", ctypes.c_int)]
+                ("landau_tol", ctypes.c_double), ("landau_maxit", ctypes.c_int), ("landau_method", ctypes.c_int),
+                ("nz", ctypes.c_int), ("bc_z", ctypes.c_int)]
 
 
 class Problem(ctypes.Structure):
@@ -91,6 +93,7 @@ def lib():
     L.rlbm_population_bytes.argtypes = [vp, ci, ci]
     L.rlbm_population_bytes.restype = ctypes.c_size_t
     L.rlbm_init_fields.argtypes = [vp, ctypes.POINTER(LatticeDesc), vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.rlbm_check_lattice.argtypes = [ctypes.POINTER(StencilDesc), ctypes.POINTER(LatticeDesc)]
     L.rlbm_step.argtypes = [vp, ci, vp]
     L.rlbm_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.rlbm_get_health.argtypes = [vp, ctypes.POINTER(ctypes.c_uint), ctypes.POINTER(ctypes.c_ulonglong),
@@ -123,6 +126,7 @@ def lib():
     L.rlbm_batch_init.argtypes = [vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
     L.rlbm_batch_step_persistent.argtypes = [vp, ci, ci, vp, vp]
     L.rlbm_batch_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.rlbm_batch_occupancy.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci), ctypes.POINTER(ci)]
     L.rlbm_batch_get_health.argtypes = [vp, ctypes.POINTER(ctypes.c_uint), ctypes.POINTER(ctypes.c_ulonglong),
                                         ctypes.POINTER(ctypes.c_uint), vp]
     L.rlbm_last_error.argtypes = [vp]
@@ -144,6 +148,22 @@ def make_desc(bases, zeta, v0=0.0, dim=2, precision="fp64", n_ref=1.0, T_ref=1.0
                     float(v0_lo), float(v0_hi), PRECISION[precision], float(n_ref), float(T_ref))
     d._keep = arr
     return d
+
+
+def lattice_desc(nx, ny, bc=("periodic", "periodic"), tau=1.0, landau_tol=0.0, landau_maxit=0, landau="newton"):
+    if isinstance(tau, dict):
+        return LatticeDesc(nx, ny, BC[bc[0]], BC[bc[1]], TAU_ETA_OVER_S, 0.0, tau["eta_over_s"], tau["T_R_GeV"],
+                           tau["n_unit_fm3"], tau["dx_fm"], landau_tol, landau_maxit, LANDAU[landau])
+    return LatticeDesc(nx, ny, BC[bc[0]], BC[bc[1]], TAU_CONST, float(tau), 0, 0, 0, 0, landau_tol, landau_maxit,
+                       LANDAU[landau])
+
+
+def check_lattice(bases, zeta, v0, nx, ny, dim=2, precision="fp64", **lattice):
+    """Host-only check of a lattice description (no GPU): raises RlbmError
+    with the library's reason when rlbm_init_fields would reject it."""
+    d = make_desc(bases, zeta, v0, dim, precision)
+    lat = lattice_desc(nx, ny, **lattice)
+    _check(lib().rlbm_check_lattice(ctypes.byref(d), ctypes.byref(lat)))
 
 
 def info_dict(info):
@@ -280,13 +300,7 @@ class Solver:
         ny, nx = n.shape
         for a in (n, T, ux, uy):
             assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous() and tuple(a.shape) == (ny, nx)
-        if isinstance(tau, dict):
-            lat = LatticeDesc(nx, ny, BC[bc[0]], BC[bc[1]], TAU_ETA_OVER_S, 0.0, tau["eta_over_s"],
-                              tau["T_R_GeV"], tau["n_unit_fm3"], tau["dx_fm"], landau_tol, landau_maxit,
-                              LANDAU[landau])
-        else:
-            lat = LatticeDesc(nx, ny, BC[bc[0]], BC[bc[1]], TAU_CONST, float(tau), 0, 0, 0, 0,
-                              landau_tol, landau_maxit, LANDAU[landau])
+        lat = lattice_desc(nx, ny, bc, tau, landau_tol, landau_maxit, landau)
         nbytes = self.population_bytes(nx, ny)
         self.pop = [torch.empty(nbytes, dtype=torch.uint8, device=n.device) for _ in range(2)]
         self._fields = (n, T, ux, uy)
@@ -432,6 +446,12 @@ class Batch:
         _check(lib().rlbm_batch_moments(self.h, out["n"].data_ptr(), out["eps"].data_ptr(), out["T"].data_ptr(),
                                         out["P"].data_ptr(), out["ux"].data_ptr(), self._stream()))
         return out
+
+    def occupancy(self):
+        """Cooperative grid of the step: workgroups launched, resident limit, tiles."""
+        w, r, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().rlbm_batch_occupancy(self.h, ctypes.byref(w), ctypes.byref(r), ctypes.byref(t)))
+        return {"workgroups": w.value, "resident_limit": r.value, "tiles": t.value}
 
     def health(self):
         f = ctypes.c_uint()

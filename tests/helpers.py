@@ -52,3 +52,16 @@ def rel_err(a, b):
 
 def field_errors(gpu, ref, keys=FIELDS):
     return {k: rel_err(gpu[k], ref[k]) for k in keys}
+
+
+def build_batch(problems, fields, v0s=None):
+    """The batched launch of `problems` (workloads.batched_riemann), one
+    float32 1D stencil context per problem at its own mbar; v0s overrides
+    each problem's v0 (0: the library's own window midpoint)."""
+    import torch
+    from paper_1703_04605_amd import rlbm
+    stencils = [rlbm.Solver(p["bases"], p["zeta"], p["v0"] if v0s is None else v0s[i], dim=1, precision="fp32")
+                for i, p in enumerate(problems)]
+    b = rlbm.Batch(stencils, [dict(p, stencil=i) for i, p in enumerate(problems)])
+    b.init(*[torch.tensor(a, dtype=torch.float64, device="cuda:0") for a in fields])
+    return b

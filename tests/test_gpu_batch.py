@@ -1,12 +1,17 @@
-"""The batched persistent launch (many independent 1D shock tubes with their
-own stencils, eta/s and pressure ratios) against per-problem oracle runs."""
+"""The batched persistent launch (many independent 1D shock tubes, each with
+its own stencil at its own mass, eta/s and pressure ratio) against
+per-problem oracle runs over the full 500-step horizon."""
+import json
+import os
+
 import numpy as np
 import pytest
 
 import workloads
-from tests.helpers import oracle_run, to_dev
+from tests.helpers import build_batch, oracle_run
 
 pytestmark = pytest.mark.gpu
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -16,40 +21,39 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def build(problems, fields):
-    import torch
-    from paper_1703_04605_amd import rlbm
-    names = sorted({p["stencil_name"] for p in problems})
-    stencils = []
-    for nm in names:
-        st = workloads.STENCILS[nm]
-        stencils.append(rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=1, precision="fp32"))
-    probs = [dict(p, stencil=names.index(p["stencil_name"])) for p in problems]
-    b = rlbm.Batch(stencils, probs)
-    b.init(*[torch.tensor(a, dtype=torch.float64, device="cuda:0") for a in fields])
-    return b
-
-
-def test_batch_matches_oracle():
-    problems, fields = workloads.batched_riemann(nprob=6, seed=3, lmin=256, lmax=420)
-    b = build(problems, fields)
-    steps = 60
-    samples = b.step(steps, sample_every=20)
+def test_batch_matches_oracle_full_horizon():
+    """Eight problems with mbar drawn continuously (two clamped to 0.36) over
+    all four stencil bands; v0 = the middle of the window that the oracle's
+    own quadrature solver finds (tests/golden/batch_windows.json), the same
+    for both sides.  Fields at steps 250 and 500 within 1e-5 of the oracle;
+    no health flag raised."""
+    problems, fields = workloads.batched_riemann(nprob=8, seed=3, lmax=512)
+    win = json.load(open(os.path.join(ROOT, "tests", "golden", "batch_windows.json")))["problems"]
+    assert [w["zeta"] for w in win] == [p["zeta"] for p in problems]
+    v0s = [w["v0"] for w in win]
+    b = build_batch(problems, fields, v0s)
+    assert {p["band"] for p in problems} == {"s133", "s46", "s73", "s57"}
+    samples = b.step(250, sample_every=50)
+    mid = {k: v.cpu().numpy() for k, v in b.moments().items()}
+    b.step(250)
     out = {k: v.cpu().numpy() for k, v in b.moments().items()}
-    assert b.health()["flags"] == 0
+    h = b.health()
+    assert h["flags"] == 0, h
     off = 0
     n, T, ux = fields
-    for p in problems:
+    for p, v0 in zip(problems, v0s):
         L = p["nx"]
         sl = slice(off, off + L)
         tau = {k: p[k] for k in ("eta_over_s", "T_R_GeV", "n_unit_fm3", "dx_fm")}
         f1 = (n[sl][None], T[sl][None], ux[sl][None], np.zeros((1, L)))
-        r = oracle_run(workloads.STENCILS[p["stencil_name"]], f1, steps, dim=1, bc=("outflow", "periodic"),
-                       tau=tau, checkpoints=[0, steps])
-        for k in ("n", "eps", "T", "P", "ux"):
-            ref = r[steps][k][0]
-            scale = np.abs(ref).max() if k != "ux" else max(np.abs(ref).max(), 1e-3)
-            assert np.abs(out[k][sl] - ref).max() < 1e-5 * scale, (p["stencil_name"], k)
+        st = {"bases": p["bases"], "zeta": p["zeta"], "v0": v0}
+        r = oracle_run(st, f1, 500, dim=1, bc=("outflow", "periodic"), tau=tau, checkpoints=[0, 250, 500])
+        for step, got in ((250, mid), (500, out)):
+            for k in ("n", "eps", "T", "P", "ux"):
+                ref = r[step][k][0]
+                scale = np.abs(ref).max() if k != "ux" else max(np.abs(ref).max(), 1e-3)
+                err = np.abs(got[k][sl] - ref).max() / scale
+                assert err < 1e-5, (p["band"], p["zeta"], step, k, err)
         # sample 0 is the initial state: moments and converged frame of f^eq
         s0 = samples[0].cpu().numpy()[sl]
         assert np.abs(s0[:, 9] - r[0]["eps"][0]).max() < 1e-5 * np.abs(r[0]["eps"]).max()
@@ -58,11 +62,16 @@ def test_batch_matches_oracle():
 
 
 def test_batch_64_problems_full_horizon_healthy():
-    """The full 64-problem, 500-step workload in one launch stays healthy."""
+    """The full 64-problem, 500-step workload in one launch over the whole
+    chip: no health flag of any kind, finite fields, and a grid of one wave
+    per 64-site tile within the device's resident limit."""
     problems, fields = workloads.batched_riemann(nprob=64, seed=0)
-    b = build(problems, fields)
+    b = build_batch(problems, fields)
+    occ = b.occupancy()
+    assert occ["tiles"] == sum((p["nx"] + 63) // 64 for p in problems)
+    assert occ["workgroups"] == min((occ["tiles"] + 3) // 4, occ["resident_limit"])
     b.step(500)
     h = b.health()
     out = b.moments()
-    assert h["flags"] & 0b1101 == 0, h
+    assert h["flags"] == 0, h
     assert np.isfinite(out["T"].cpu().numpy()).all()

@@ -1,6 +1,6 @@
 """Edge cases of the step on the GPU: lattices smaller than the stencil's
 reach (a site's pulls wrap or clamp several times over), a single site, and
-lattice descriptions that the library must reject before it touches memory."""
+rejected lattice descriptions that leave a context usable."""
 import ctypes
 
 import numpy as np
@@ -49,49 +49,41 @@ def test_single_site_is_a_fixed_point(precision):
         assert abs(g[10][k][0, 0] - ref[0, 0]) <= tol * max(1.0, abs(ref[0, 0])), (k, g[10][k], ref)
 
 
-def test_rejects_invalid_lattices_before_any_device_work():
-    """Empty lattices, a 1D stencil on more than one row, more than 2^31 - 1
-    sites, 2^31 or more stored elements, tau <= 1/2 and an iteration cap
-    above 10^6 all return RLBM_EINVAL; a context without fields then returns
-    RLBM_ESTATE from a step.  The checks precede every device access (the
-    buffers passed here are far smaller than the sizes claimed)."""
+def test_rejected_descriptions_leave_the_context_usable():
+    """rlbm_init_fields rejects a description with RLBM_EINVAL before the
+    context changes (the same host checks as rlbm_check_lattice, covered on
+    the CPU); every buffer passed here has the size the description claims.
+    A context without fields returns RLBM_ESTATE from a step."""
     import torch
     from paper_1703_04605_amd import rlbm
+    from tests.helpers import to_dev
     L = rlbm.lib()
     st = workloads.STENCILS["zeta1"]
     s = rlbm.Solver(st["bases"], st["zeta"], st["v0"], precision="fp32")
-    f = [torch.ones(1, dtype=torch.float64, device="cuda:0") for _ in range(4)]
-    pa = torch.zeros(256, dtype=torch.uint8, device="cuda:0")
-    pb = torch.zeros(256, dtype=torch.uint8, device="cuda:0")
-    cases = [(0, 4, 1.0), (4, 0, 1.0), (65536, 32769, 1.0), (32768, 32768, 1.0), (16, 16, 0.5)]
-    for nx, ny, tau in cases:
-        lat = rlbm.LatticeDesc(nx, ny, 0, 0, rlbm.TAU_CONST, tau, 0, 0, 0, 0, 0.0, 0, 0)
-        claim = max(int(s.population_bytes(nx, ny)), 256)
-        rc = L.rlbm_init_fields(s.ctx, ctypes.byref(lat), f[0].data_ptr(), f[1].data_ptr(), f[2].data_ptr(),
-                                f[3].data_ptr(), pa.data_ptr(), pb.data_ptr(), claim, None)
-        assert rc == rlbm.RLBM_EINVAL, (nx, ny, tau, rc)
-    s1 = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=1, precision="fp64")
-    lat = rlbm.LatticeDesc(8, 2, 0, 0, rlbm.TAU_CONST, 1.0, 0, 0, 0, 0, 0.0, 0, 0)
-    rc = L.rlbm_init_fields(s1.ctx, ctypes.byref(lat), f[0].data_ptr(), f[1].data_ptr(), f[2].data_ptr(),
-                            f[3].data_ptr(), pa.data_ptr(), pb.data_ptr(), 1 << 20, None)
-    assert rc == rlbm.RLBM_EINVAL
     assert L.rlbm_step(s.ctx, 1, None) == rlbm.RLBM_ESTATE
-    # an iteration cap above 10^6 is rejected; a re-initialisation that fails
-    # at the layout limit leaves a context that had fields without them
-    from tests.helpers import to_dev
     g = to_dev(workloads.random_smooth(16, 8, seed=1))
     s.init_fields(*g)
-    nb = int(s.population_bytes(16, 8))     # real buffers of the claimed size for this case
+    nb = int(s.population_bytes(16, 8))
     qa = torch.zeros(nb, dtype=torch.uint8, device="cuda:0")
     qb = torch.zeros(nb, dtype=torch.uint8, device="cuda:0")
-    lat = rlbm.LatticeDesc(16, 8, 0, 0, rlbm.TAU_CONST, 1.0, 0, 0, 0, 0, 0.0, 2000000, 0)
+    for maxit, tau, method in ((2000000, 1.0, 0), (0, 0.5, 0), (0, 1.0, 7)):
+        lat = rlbm.LatticeDesc(16, 8, 0, 0, rlbm.TAU_CONST, tau, 0, 0, 0, 0, 0.0, maxit, method)
+        rc = L.rlbm_init_fields(s.ctx, ctypes.byref(lat), g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(),
+                                g[3].data_ptr(), qa.data_ptr(), qb.data_ptr(), nb, None)
+        assert rc == rlbm.RLBM_EINVAL, (maxit, tau, method)
+    lat = rlbm.LatticeDesc(16, 8, 0, 0, rlbm.TAU_CONST, 1.0, 0, 0, 0, 0, 0.0, 0, 0)
     rc = L.rlbm_init_fields(s.ctx, ctypes.byref(lat), g[0].data_ptr(), g[1].data_ptr(), g[2].data_ptr(),
-                            g[3].data_ptr(), qa.data_ptr(), qb.data_ptr(), nb, None)
-    assert rc == rlbm.RLBM_EINVAL
-    s.step(1)                       # rejected before the context changed: still usable
-    lat = rlbm.LatticeDesc(32768, 32768, 0, 0, rlbm.TAU_CONST, 1.0, 0, 0, 0, 0, 0.0, 0, 0)
-    rc = L.rlbm_init_fields(s.ctx, ctypes.byref(lat), f[0].data_ptr(), f[1].data_ptr(), f[2].data_ptr(),
-                            f[3].data_ptr(), pa.data_ptr(), pb.data_ptr(), int(s.population_bytes(32768, 32768)),
-                            None)
-    assert rc == rlbm.RLBM_EINVAL
-    assert L.rlbm_step(s.ctx, 1, None) == rlbm.RLBM_ESTATE
+                            g[3].data_ptr(), qa.data_ptr(), qb.data_ptr(), nb - 1, None)
+    assert rc == rlbm.RLBM_EINVAL                      # buffer one byte short
+    s.step(1)                       # every rejection came before the context changed: still usable
+    torch.cuda.synchronize()
+    s1 = rlbm.Solver(st["bases"], st["zeta"], st["v0"], dim=1, precision="fp64")
+    nb1 = int(s1.population_bytes(8, 2))
+    ra = torch.zeros(nb1, dtype=torch.uint8, device="cuda:0")
+    rb = torch.zeros(nb1, dtype=torch.uint8, device="cuda:0")
+    h = to_dev(workloads.random_smooth(8, 2, seed=2))
+    lat = rlbm.LatticeDesc(8, 2, 0, 0, rlbm.TAU_CONST, 1.0, 0, 0, 0, 0, 0.0, 0, 0)
+    rc = L.rlbm_init_fields(s1.ctx, ctypes.byref(lat), h[0].data_ptr(), h[1].data_ptr(), h[2].data_ptr(),
+                            h[3].data_ptr(), ra.data_ptr(), rb.data_ptr(), nb1, None)
+    assert rc == rlbm.RLBM_EINVAL                      # a 1D stencil on two rows
+    assert L.rlbm_step(s1.ctx, 1, None) == rlbm.RLBM_ESTATE

@@ -107,3 +107,46 @@ def test_inverse_eos_table_against_oracle(zeta):
     # bounded by the conditioning of the inversion: ulp(e)/c_v with c_v >= 3/2
     err = np.abs(Tl - T) / (np.finfo(float).eps * (e / 1.5 + T))
     assert err.max() < 8.0, err.max()
+
+
+def test_lattice_checks_on_the_host():
+    """rlbm_check_lattice (no GPU) rejects what rlbm_init_fields rejects
+    before it touches the device: empty lattices, a 1D stencil on more than
+    one row, more than 2^31 - 1 sites, 2^31 or more stored elements, tau <=
+    1/2, unknown tau modes, boundary rules and Landau methods, an iteration
+    cap above 10^6, and an eta/s rule without its physical units."""
+    st = workloads.STENCILS["zeta1"]
+    args = (st["bases"], st["zeta"], st["v0"])
+    ok = [dict(nx=16, ny=8), dict(nx=4096, ny=4096), dict(nx=3, ny=2, bc=("outflow", "outflow")),
+          dict(nx=1, ny=1), dict(nx=800, ny=1, tau={"eta_over_s": 0.1, "T_R_GeV": 0.26, "n_unit_fm3": 15.5,
+                                                     "dx_fm": 0.008})]
+    for kw in ok:
+        rlbm.check_lattice(*args, precision="fp32", **kw)
+    bad = [dict(nx=0, ny=4), dict(nx=4, ny=0), dict(nx=65536, ny=32769), dict(nx=32768, ny=32768),
+           dict(nx=16, ny=16, tau=0.5), dict(nx=16, ny=16, landau_maxit=2000000),
+           dict(nx=16, ny=16, landau="bogus"), dict(nx=16, ny=16, tau={"eta_over_s": 0.1, "T_R_GeV": 0.26,
+                                                                      "n_unit_fm3": 0.0, "dx_fm": 0.008})]
+    for kw in bad:
+        if kw.get("landau") == "bogus":
+            d = rlbm.make_desc(*args, precision="fp32")
+            lat = rlbm.lattice_desc(16, 16)
+            lat.landau_method = 7
+            assert rlbm.lib().rlbm_check_lattice(d, lat) == rlbm.RLBM_EINVAL
+            lat = rlbm.lattice_desc(16, 16)
+            lat.bc_x = 2
+            assert rlbm.lib().rlbm_check_lattice(d, lat) == rlbm.RLBM_EINVAL
+            lat = rlbm.lattice_desc(16, 16)
+            lat.tau_mode = 5
+            assert rlbm.lib().rlbm_check_lattice(d, lat) == rlbm.RLBM_EINVAL
+            continue
+        with pytest.raises(rlbm.RlbmError) as e:
+            rlbm.check_lattice(*args, precision="fp32", **kw)
+        assert e.value.code == rlbm.RLBM_EINVAL, kw
+    # a 1D stencil on two rows; the stored-element limit (44 class rows of
+    # 4160 or 8256 elements per lattice row, plus 8 ghost rows)
+    with pytest.raises(rlbm.RlbmError):
+        rlbm.check_lattice(*args, dim=1, nx=8, ny=2)
+    rlbm.check_lattice(*args, dim=1, nx=8, ny=1)
+    rlbm.check_lattice(*args, precision="fp16", nx=4096, ny=8192)
+    with pytest.raises(rlbm.RlbmError):
+        rlbm.check_lattice(*args, precision="fp16", nx=8192, ny=8192)

@@ -80,3 +80,20 @@ def test_base_vectors_are_the_group_table():
     for n2 in (18, 29, 45):
         want = {b for b in table if 0 < sum(c * c for c in b) <= n2}
         assert set(sr.base_vectors(n2)) == want, n2
+
+
+def test_library_windows_match_oracle_windows_of_the_batch_subset():
+    """The positive-weight v0 windows the library's host solver finds for the
+    continuous-mbar batch subset agree with the oracle's own windows
+    (tests/golden/batch_windows.json, written by make_batch_windows.py)."""
+    import json
+    import os
+    from paper_1703_04605_amd import rlbm
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    win = json.load(open(os.path.join(root, "tests", "golden", "batch_windows.json")))["problems"]
+    for w in win:
+        info = rlbm.solve_stencil([tuple(b) for b in w["bases"]], w["zeta"], 0.0, dim=1)
+        width = w["v0_hi"] - w["v0_lo"]
+        assert abs(info["v0_lo"] - w["v0_lo"]) < 1e-6 * width + 1e-13, w
+        assert abs(info["v0_hi"] - w["v0_hi"]) < 1e-6 * width + 1e-13, w
+        assert w["v0_lo"] < info["v0"] < w["v0_hi"]

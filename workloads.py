@@ -101,26 +101,48 @@ def random_smooth(nx, ny, seed=0, umax=0.3):
     return n, T, ux, uy
 
 
-# stencils available for the batched workload, by mbar
-BATCH_ZETAS = {0.36: "zeta036", 1.0: "zeta1", 5.0: "zeta5", 10.0: "zeta10"}
+# Stencils of the batched workload, by mbar band: each band lies inside the
+# stencil's working range (positive weights for some v0), and together they
+# cover [0.36, 10] without a gap:
+#   s133: the paper's 133-population stencil (Fig. 6), works on [0.3585, 0.5823]
+#   s46:  46 populations, works on [0.486, 1.185]
+#   s73:  73 populations, works on [1.025, > 8]
+#   s57:  G1..G6 (57 populations), works on [4.01, > 40]
+BATCH_BANDS = [
+    (0.36, 0.52, "s133", [(0, 0, 0), (3, 3, 0), (5, 4, 2), (5, 3, 3), (6, 3, 0), (6, 2, 2)]),
+    (0.52, 1.10, "s46", [(0, 0, 0), (3, 3, 0), (5, 0, 0), (5, 1, 0), (3, 3, 3), (5, 1, 1)]),
+    (1.10, 6.00, "s73", [(0, 0, 0), (2, 0, 0), (2, 1, 1), (2, 2, 0), (2, 2, 1), (3, 0, 0)]),
+    (6.00, 10.0, "s57", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 1), (2, 0, 0), (2, 1, 0)]),
+]
+BATCH_ZETA_MIN = 0.36   # no second-order stencil has positive weights much below 0.3585
+
+
+def batch_band(zeta):
+    """(name, bases) of the stencil whose band holds mbar = zeta."""
+    for lo, hi, name, bases in BATCH_BANDS:
+        if lo <= zeta < hi or (hi == BATCH_BANDS[-1][1] and zeta == hi):
+            return name, bases
+    raise ValueError(f"mbar {zeta} outside [{BATCH_BANDS[0][0]}, {BATCH_BANDS[-1][1]}]")
 
 
 def batched_riemann(nprob=64, seed=0, lmin=256, lmax=4096, zeta_range=(0.1, 10.0), eta_s_range=(0.05, 0.5),
                     ratio_range=(2.0, 50.0), dx_fm=0.002):
     """Independent quasi-1D shock tubes: length L ~ U{lmin..lmax}, mbar drawn
-    log-uniform in zeta_range and snapped (in log) to the nearest available
-    stencil, eta/s uniform, pressure ratio r log-uniform.  Left state
+    log-uniform in zeta_range and clamped to [0.36, 10] (below 0.3585 no
+    second-order stencil exists), each problem with the stencil of its band
+    at its own mbar (v0 = 0: the middle of the stencil's positive-weight
+    window), eta/s uniform, pressure ratio r log-uniform.  Left state
     T = 0.35 GeV, P = 5.43 GeV/fm^3; right state T r^(-1/4), n r^(-3/4) (P ~ T^4);
     T_R the geometric mean of the two temperatures; dx = 0.002 fm (the
     paper's lattice spacing); u = 0; interface at L/2.
     Returns (problems, fields) with fields = (n, T, ux) concatenated."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    zs = np.array(sorted(BATCH_ZETAS))
     probs, ns, Ts, us = [], [], [], []
     for _ in range(nprob):
         L = int(rng.integers(lmin, lmax + 1))
         zeta_drawn = float(np.exp(rng.uniform(np.log(zeta_range[0]), np.log(zeta_range[1]))))
-        zeta = float(zs[np.argmin(np.abs(np.log(zs) - np.log(zeta_drawn)))])
+        zeta = min(max(zeta_drawn, BATCH_ZETA_MIN), BATCH_BANDS[-1][1])
+        band, bases = batch_band(zeta)
         eta_s = float(rng.uniform(*eta_s_range))
         r = float(np.exp(rng.uniform(np.log(ratio_range[0]), np.log(ratio_range[1]))))
         TL, TRt = 0.35, 0.35 * r ** -0.25
@@ -129,6 +151,6 @@ def batched_riemann(nprob=64, seed=0, lmin=256, lmax=4096, zeta_range=(0.1, 10.0
         ns.append(np.where(left, 1.0, r ** -0.75))
         Ts.append(np.where(left, TL / TR, TRt / TR))
         us.append(np.zeros(L))
-        probs.append({"nx": L, "stencil_name": BATCH_ZETAS[zeta], "zeta_drawn": zeta_drawn, "zeta": zeta,
+        probs.append({"nx": L, "band": band, "bases": bases, "zeta_drawn": zeta_drawn, "zeta": zeta, "v0": 0.0,
                       "eta_over_s": eta_s, "ratio": r, "T_R_GeV": TR, "n_unit_fm3": 5.43 / 0.35, "dx_fm": dx_fm})
     return probs, (np.concatenate(ns), np.concatenate(Ts), np.concatenate(us))
