@@ -200,6 +200,23 @@ int rlbm_init_fields(rlbm_ctx* ctx, const rlbm_lattice_desc* lat, const double* 
 int rlbm_check_lattice(const rlbm_stencil_desc* desc, const rlbm_lattice_desc* lat);
 
 /*
+ * Allocation-free form of rlbm_init_fields, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops that set
+ * up many lattices).  Same arguments, checks, result and errors; the health
+ * slots of the lattice (one per 64 sites of a row) live in a static device
+ * array that the library holds on each GPU until the process ends, instead
+ * of library-allocated memory, so no hipMalloc or hipFree is called.  Limit:
+ * 262144 tiles (ceil(nx/64) * ny), e.g. 4096 x 4096 sites; larger lattices
+ * give RLBM_EINVAL.  One context per GPU uses the array at a time: this call
+ * drops the fields of the context that used it before (its rlbm_step then
+ * returns RLBM_ESTATE).  Calls that overlap on one GPU race (their health
+ * counters mix).
+ */
+int rlbm_init_fields_noalloc(rlbm_ctx* ctx, const rlbm_lattice_desc* lat, const double* n, const double* T,
+                             const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
+                             void* stream);
+
+/*
  * Advances nsteps time steps (collide, then stream; eq.
  * discrete-relativistic-boltzmann): per site, moments N^a, T^ab
  * (eq. mj-discrete-second-moment), Landau frame (eqs. landau-lifshitz-*),

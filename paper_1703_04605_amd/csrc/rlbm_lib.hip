@@ -18,6 +18,7 @@
 
 #include <algorithm>
 #include <memory>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 #include <cmath>
@@ -1110,9 +1111,10 @@ struct rlbm_ctx {
   int cur = 0;
   int shifted = 0;
   long long steps = 0;
-  RlbmSlot* slots = nullptr;    // health slots in use
+  RlbmSlot* slots = nullptr;    // health slots in use: d_slots, or the static array
   RlbmSlot* d_slots = nullptr;  // library-allocated health slots
   int nslots = 0;               // capacity of d_slots
+  bool static_slots = false;    // slots live in the device's static array
   int tiles_x = 0, ntiles = 0;  // wave tiles (kWave sites of a row); one health slot each
   double tk1 = 0, tk2 = 0;
   const rlbm_mlp* guess = nullptr;
@@ -1173,9 +1175,72 @@ extern "C" int rlbm_init_stencil(rlbm_ctx** out, const rlbm_stencil_desc* desc, 
   return RLBM_OK;
 }
 
+// ------------------------------------------------------------------ static health slots
+//
+// The allocation-free field set-up keeps the health slots of its lattice in
+// one file-scope device array instead of library-allocated memory.  Each GPU
+// holds its own copy of the array (until the process ends), found once per
+// device with hipGetSymbolAddress; host code uses only that address, never
+// the array's name.  One context per device owns it at a time: a context
+// that takes it over drops the fields of the previous owner (whose later
+// rlbm_step then returns RLBM_ESTATE), so no step of a context ever writes
+// another lattice's slots.  Steps of the previous owner that are still in
+// flight when the array changes hands write slots below that owner's tile
+// count, which stays inside the array; only its health counters are mixed up
+// (calls that overlap on one GPU race).
+constexpr int kStaticSlots = 262144;  // 4 MiB: one slot per 64-site tile, e.g. a 4096 x 4096 lattice
+static __device__ __align__(256) RlbmSlot scratch[kStaticSlots];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+RlbmSlot* g_static_ptr[kMaxDevices] = {};
+rlbm_ctx* g_static_owner[kMaxDevices] = {};
+}  // namespace
+
+// Address of this device's static slot array (resolved once per device, with
+// that device current); nullptr and *why on failure.
+static RlbmSlot* static_slots_of(int device, const char** why) {
+  if (device < 0 || device >= kMaxDevices) {
+    *why = "device index beyond the static-slot table";
+    return nullptr;
+  }
+  if (!g_static_ptr[device]) {
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) {
+      *why = "hipGetDevice failed";
+      return nullptr;
+    }
+    if (prev != device && hipSetDevice(device) != hipSuccess) {
+      *why = "hipSetDevice failed";
+      return nullptr;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess || !p) {
+      *why = "hipGetSymbolAddress of the static slot array failed";
+      return nullptr;
+    }
+    g_static_ptr[device] = (RlbmSlot*)p;
+  }
+  return g_static_ptr[device];
+}
+
+// Gives up c's claim on its device's static slot array (caller holds g_static_mu).
+static void release_static_slots(rlbm_ctx* c) {
+  if (c->device >= 0 && c->device < kMaxDevices && g_static_owner[c->device] == c) g_static_owner[c->device] = nullptr;
+  if (c->static_slots) c->slots = nullptr;
+  c->static_slots = false;
+}
+
 extern "C" int rlbm_destroy(rlbm_ctx* c) {
   if (!c) return RLBM_OK;
   (void)hipDeviceSynchronize();
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    release_static_slots(c);
+  }
   if (c->d_tab) (void)hipFree(c->d_tab);
   if (c->d_slots) (void)hipFree(c->d_slots);
   if (c->d_warm) (void)hipFree(c->d_warm);
@@ -1296,9 +1361,12 @@ __global__ void __launch_bounds__(kBlock) k_fields_setup(RlbmOffsetsArg o, RlbmT
   if (i < nslots) slots[i] = RlbmSlot{0u, 0u, 0ull};
 }
 
+// Shared body of rlbm_init_fields and rlbm_init_fields_noalloc.  With
+// use_static the health slots live in the device's static array and nothing
+// is allocated.
 static int init_fields_impl(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n, const double* T,
                             const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
-                            void* stream) {
+                            void* stream, bool use_static) {
   if (!c || !lat) return fail(c, RLBM_EINVAL, "NULL context or lattice");
   const RlbmConsts& k = c->h_tab->c;
   RlbmLayout L;
@@ -1310,18 +1378,44 @@ static int init_fields_impl(rlbm_ctx* c, const rlbm_lattice_desc* lat, const dou
   if (pop_bytes < need) return fail(c, RLBM_EINVAL, "population buffer too small");
   const int tiles_x = (lat->nx + kWave - 1) / kWave;
   const long long ntiles = (long long)tiles_x * lat->ny;
+  if (use_static && ntiles > kStaticSlots)
+    return fail(c, RLBM_EINVAL, "%s",
+                "lattice too large for the allocation-free set-up (more than 262144 tiles of 64 sites of a row)");
   hipStream_t s = (hipStream_t)stream;
 
   // from here on the context is being rebuilt: a failure leaves it without fields
   c->have_fields = false;
-  if (ntiles > c->nslots) {
-    if (c->d_slots) HIPCHECK(c, hipFree(c->d_slots));
-    c->d_slots = nullptr;
-    c->nslots = 0;
-    HIPCHECK(c, hipMalloc((void**)&c->d_slots, sizeof(RlbmSlot) * ntiles));
-    c->nslots = (int)ntiles;
+  RlbmSlot* slots = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (use_static) {
+      const char* why = nullptr;
+      slots = static_slots_of(c->device, &why);
+      if (!slots) return fail(c, RLBM_EHIP, "%s", why);
+      rlbm_ctx* prev = g_static_owner[c->device];
+      if (prev && prev != c) {
+        // the previous owner loses its fields (its slots are about to be reused)
+        prev->have_fields = false;
+        release_static_slots(prev);
+        snprintf(prev->err, sizeof(prev->err), "%s",
+                 "fields dropped: another context took the allocation-free health slots of this device");
+      }
+      g_static_owner[c->device] = c;
+      c->static_slots = true;
+    } else {
+      release_static_slots(c);
+    }
   }
-  RlbmSlot* slots = c->d_slots;
+  if (!use_static) {
+    if (ntiles > c->nslots) {
+      if (c->d_slots) HIPCHECK(c, hipFree(c->d_slots));
+      c->d_slots = nullptr;
+      c->nslots = 0;
+      HIPCHECK(c, hipMalloc((void**)&c->d_slots, sizeof(RlbmSlot) * ntiles));
+      c->nslots = (int)ntiles;
+    }
+    slots = c->d_slots;
+  }
   c->slots = slots;
   c->lat = *lat;
   c->warm = false;
@@ -1365,7 +1459,13 @@ static int init_fields_impl(rlbm_ctx* c, const rlbm_lattice_desc* lat, const dou
 extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n, const double* T,
                                 const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
                                 void* stream) {
-  return init_fields_impl(c, lat, n, T, ux, uy, popA, popB, pop_bytes, stream);
+  return init_fields_impl(c, lat, n, T, ux, uy, popA, popB, pop_bytes, stream, false);
+}
+
+extern "C" int rlbm_init_fields_noalloc(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n,
+                                        const double* T, const double* ux, const double* uy, void* popA,
+                                        void* popB, size_t pop_bytes, void* stream) {
+  return init_fields_impl(c, lat, n, T, ux, uy, popA, popB, pop_bytes, stream, true);
 }
 
 extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {

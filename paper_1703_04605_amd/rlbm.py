@@ -35,7 +35,7 @@ EXPORTS = ["rlbm_init_stencil", "rlbm_solve_stencil", "rlbm_class_table", "rlbm_
            "rlbm_landau_guess_fields", "rlbm_batch_create", "rlbm_batch_destroy", "rlbm_batch_population_bytes",
            "rlbm_batch_sites", "rlbm_batch_init", "rlbm_batch_step_persistent", "rlbm_batch_moments",
            "rlbm_batch_get_health", "rlbm_set_step_variant", "rlbm_step_kernel", "rlbm_check_lattice",
-           "rlbm_batch_occupancy"]
+           "rlbm_init_fields_noalloc", "rlbm_batch_occupancy"]
 
 STEP_AUTO, STEP_TABLE, STEP_FIXED = 0, 1, 2
 
@@ -93,6 +93,8 @@ def lib():
     L.rlbm_population_bytes.argtypes = [vp, ci, ci]
     L.rlbm_population_bytes.restype = ctypes.c_size_t
     L.rlbm_init_fields.argtypes = [vp, ctypes.POINTER(LatticeDesc), vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.rlbm_init_fields_noalloc.argtypes = [vp, ctypes.POINTER(LatticeDesc), vp, vp, vp, vp, vp, vp,
+                                           ctypes.c_size_t, vp]
     L.rlbm_check_lattice.argtypes = [ctypes.POINTER(StencilDesc), ctypes.POINTER(LatticeDesc)]
     L.rlbm_step.argtypes = [vp, ci, vp]
     L.rlbm_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -293,9 +295,11 @@ class Solver:
         return lib().rlbm_population_bytes(self.ctx, nx, ny)
 
     def init_fields(self, n, T, ux, uy, bc=("periodic", "periodic"), tau=1.0, landau_tol=0.0, landau_maxit=0,
-                    landau="newton"):
+                    landau="newton", noalloc=False):
         """n, T, ux, uy: CUDA float64 tensors [ny, nx].  tau: float, or dict with
-        eta_over_s, T_R_GeV, n_unit_fm3, dx_fm for the eta/s rule."""
+        eta_over_s, T_R_GeV, n_unit_fm3, dx_fm for the eta/s rule.  noalloc:
+        use rlbm_init_fields_noalloc (health slots in the library's static
+        device array)."""
         torch = self.torch
         ny, nx = n.shape
         for a in (n, T, ux, uy):
@@ -304,9 +308,9 @@ class Solver:
         nbytes = self.population_bytes(nx, ny)
         self.pop = [torch.empty(nbytes, dtype=torch.uint8, device=n.device) for _ in range(2)]
         self._fields = (n, T, ux, uy)
-        _check(lib().rlbm_init_fields(self.ctx, ctypes.byref(lat), n.data_ptr(), T.data_ptr(), ux.data_ptr(),
-                                      uy.data_ptr(), self.pop[0].data_ptr(), self.pop[1].data_ptr(), nbytes,
-                                      self._stream()), self.ctx)
+        fn = lib().rlbm_init_fields_noalloc if noalloc else lib().rlbm_init_fields
+        _check(fn(self.ctx, ctypes.byref(lat), n.data_ptr(), T.data_ptr(), ux.data_ptr(), uy.data_ptr(),
+                  self.pop[0].data_ptr(), self.pop[1].data_ptr(), nbytes, self._stream()), self.ctx)
         self.nx, self.ny = nx, ny
 
     def step(self, nsteps=1):
