@@ -23,7 +23,9 @@ workload:
   * batched_riemann: 64 independent 1D shock tubes, 500 steps, one launch;
   * riemann_800: the 800 x 1 shock tube (float64, eta/s = 0.1, 500 steps;
     launch bound);
-  * copy: a device-to-device copy, the achievable HBM ceiling.
+  * taylor_green_3d: a 256 x 256 x 128 lattice with every population of the
+    stencil (Sec. V), float64 / float32 / float16;
+  * copy: the library's streaming device copy, the achievable HBM ceiling.
 cpu_baseline times the float64 oracle on the host's cores on strips of the
 headline workload.
 """
@@ -111,14 +113,14 @@ def run_path(st, fields, precision, steps, warmup, tau=1.0, landau="newton", gue
     return rec, out
 
 
-def field_errors(a, b, vnorm=None):
+def field_errors(a, b, vnorm=None, keys=FIELDS):
     """max |a - b| / max |b| per field; velocities optionally normalised by a
     given speed instead (fields whose own maximum is tiny)."""
     import numpy as np
     res = {}
-    for k in FIELDS:
+    for k in keys:
         scale = float(np.abs(b[k]).max())
-        if vnorm is not None and k in ("ux", "uy"):
+        if vnorm is not None and k in ("ux", "uy", "uz"):
             scale = vnorm
         res[k] = float(np.abs(a[k] - b[k]).max() / (scale if scale > 0 else 1.0))
     return res
@@ -215,24 +217,77 @@ def time_riemann_800(steps=500):
             "health_flags": s.health()["flags"], "note": "800 sites: one launch per step, launch bound"}
 
 
-def copy_bandwidth(nbytes=4 << 30, reps=10):
-    """Device-to-device copy of nbytes, bytes read plus written per second."""
+def time_3d(shape=(128, 256, 256), steps=200):
+    """3D Taylor-Green vortex (Sec. V), every population of the stencil:
+    float64, float32 and float16 for G1..G6 (zeta = 5, 57 populations), and
+    float32 for the zeta = 1 stencil (67), each against its float64 run."""
     import torch
+    import workloads
+    from paper_1703_04605_amd import rlbm
+    from tests.helpers import to_dev
+    nz, ny, nx = shape
+    sites = nx * ny * nz
+    f = to_dev(workloads.taylor_green_3d(nx, ny, nz, seed=0))
+    out = {"workload": f"3D Taylor-Green {nx} x {ny} x {nz}, tau 1, {steps} steps"}
+    for name in ("zeta5", "zeta1"):
+        st = workloads.STENCILS[name]
+        runs, res = {}, {}
+        for prec in (("fp64", "fp32", "fp16") if name == "zeta5" else ("fp64", "fp32")):
+            s = rlbm.Solver3D(st["bases"], st["zeta"], st["v0"], precision=prec)
+            s.init_fields(*f, tau=1.0)
+            s.step(10)
+            s.health(reset=True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            s.step(steps)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            h = s.health()
+            q = s.info["q"]
+            gbs = 2 * q * ELEM[prec] * sites / (ms * 1e-3) / 1e9
+            res[prec] = {"mlups": sites / (ms * 1e-3) / 1e6, "ms_per_step": ms, "hbm_gbs": gbs,
+                         "hbm_frac": gbs / HBM_PEAK_GBS, "landau_iter_mean": h["iter_sum"] / (sites * steps),
+                         "health_flags": h["flags"], "populations": q}
+            runs[prec] = {k: v.cpu().numpy() for k, v in s.moments().items()}
+            del s
+            torch.cuda.empty_cache()
+        for prec in res:
+            if prec != "fp64":
+                res[prec]["max_rel_err_vs_fp64"] = field_errors(runs[prec], runs["fp64"], vnorm=0.3,
+                                                                keys=FIELDS + ("uz",))
+        out[name] = res
+    return out
+
+
+def copy_bandwidth(nbytes=4 << 30, reps=10):
+    """The achievable HBM rate: the library's streaming copy of nbytes (bytes
+    read plus written per second), best grid of a few; torch's copy beside it."""
+    import torch
+    from paper_1703_04605_amd import rlbm
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     a.fill_(1)
-    b.copy_(a)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+
+    def rate(fn):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return 2 * nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
+
+    grids = {wg: rate(lambda: rlbm.device_copy(b, a, wg)) for wg in (16384, 65536, 262144)}
+    best = max(grids, key=grids.get)
+    res = {"gbs": grids[best], "bytes": nbytes, "workgroups": best, "by_grid": grids,
+           "torch_copy_gbs": rate(lambda: b.copy_(a))}
     del a, b
     torch.cuda.empty_cache()
-    return {"gbs": 2 * nbytes / (ms * 1e-3) / 1e9, "bytes": nbytes, "ms": ms}
+    return res
 
 
 def _oracle_worker(args):
@@ -289,6 +344,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16-4096", action="store_true", help="skip the 4096^2 float16 flows")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="also run one 256 MiB device copy (scales the profiler's byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: runs on one GPU; --gpus {args.gpus} is not supported "
@@ -303,6 +360,13 @@ def main():
     import workloads
     from tests.helpers import to_dev
 
+    if args.calibration_copy:
+        from paper_1703_04605_amd import rlbm
+        src = torch.ones(1 << 28, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        rlbm.device_copy(dst, src)
+        torch.cuda.synchronize()
+        del src, dst
     st = workloads.STENCILS["zeta1"]
     N = 2048
     kh = to_dev(workloads.kelvin_helmholtz(N, N, seed=0))
@@ -375,6 +439,7 @@ def main():
                 torch.cuda.empty_cache()
             del khb
             paths["sheared_flow_4096_fp16"] = {"workload": "Kelvin-Helmholtz 4096^2, 5000 steps", **big}
+        paths["taylor_green_3d"] = time_3d()
         paths["batched_riemann"] = time_batched()
         paths["riemann_800"] = time_riemann_800()
     copy = copy_bandwidth()

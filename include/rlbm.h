@@ -85,7 +85,10 @@ typedef struct rlbm_ctx rlbm_ctx;
  */
 typedef struct {
   int dim;               /* 2: Nx x Ny lattice (1 x Nx x Ny slab of the 3D
-                            stencil), 1: Nx x 1 lattice */
+                            stencil), 1: Nx x 1 lattice, 3: Nx x Ny x Nz
+                            lattice with every population of the stencil
+                            (Sec. V); 3D lattices take rlbm_init_fields3 and
+                            rlbm_moments3 */
   int n_groups;          /* number of groups, 6 at second order */
   const int* group_base; /* host, 3*n_groups ints: base vectors (a, b, c) */
   double zeta;           /* mbar = m / T_R, > 0 */
@@ -215,6 +218,31 @@ int rlbm_check_lattice(const rlbm_stencil_desc* desc, const rlbm_lattice_desc* l
 int rlbm_init_fields_noalloc(rlbm_ctx* ctx, const rlbm_lattice_desc* lat, const double* n, const double* T,
                              const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
                              void* stream);
+
+/*
+ * 3D lattices (stencil dim 3; Sec. V runs the method in three dimensions as
+ * in two).  Every population of the stencil is stored (no merging), the
+ * moments are the 14 components of N^a and T^ab, the Landau frame has three
+ * velocity components (Newton on the quartic characteristic polynomial of
+ * T eta; RLBM_LANDAU_NEWTON only), the equilibrium uses all 14 projections
+ * (Appendix B) and a population streams by its 3D vector n_i.  Layout: lat->nz
+ * planes of ny storage rows of q class rows (x fastest) with ghost columns,
+ * rows and planes of the stencil's reach; bc_x, bc_y, bc_z per axis.
+ * rlbm_population_bytes3 gives the buffer size (0 for other stencils).
+ * rlbm_init_fields3 sets f = f^eq(n, T, u) from device float64 fields n, T,
+ * ux, uy, uz of nx*ny*nz values (index (z*ny + y)*nx + x), with the same
+ * ownership, checks and errors as rlbm_init_fields; rlbm_step advances it;
+ * rlbm_moments3 writes n, eps, T, P, ux, uy, uz (any may be NULL) and raw14
+ * (device float64 [14][nz][ny][nx] or NULL: N^0, N^x, N^y, N^z, T^00, T^0x,
+ * T^0y, T^0z, T^xx, T^xy, T^xz, T^yy, T^yz, T^zz) of the pre-collision
+ * state.  The learned guess and the warm start are 1D/2D only.
+ */
+size_t rlbm_population_bytes3(const rlbm_ctx* ctx, int nx, int ny, int nz);
+int rlbm_init_fields3(rlbm_ctx* ctx, const rlbm_lattice_desc* lat, const double* n, const double* T,
+                      const double* ux, const double* uy, const double* uz, void* popA, void* popB,
+                      size_t pop_bytes, void* stream);
+int rlbm_moments3(rlbm_ctx* ctx, double* n, double* eps, double* T, double* P, double* ux, double* uy, double* uz,
+                  double* raw14, void* stream);
 
 /*
  * Advances nsteps time steps (collide, then stream; eq.
@@ -369,6 +397,15 @@ int rlbm_batch_moments(rlbm_batch* b, double* n, double* eps, double* T, double*
  * (synchronises stream); RLBM_ENUMERIC if a fatal flag is set. */
 int rlbm_batch_get_health(rlbm_batch* b, unsigned* flags, unsigned long long* iter_sum, unsigned* iter_max,
                           void* stream);
+
+/*
+ * Measurement utility: copies bytes (a multiple of 16) from src to dst
+ * (device buffers, not overlapping) with a plain streaming kernel of the
+ * given number of 256-thread workgroups, asynchronously on stream.  Its rate
+ * is the achievable HBM ceiling against which the step's traffic is
+ * reported.  Errors: RLBM_EINVAL, RLBM_EHIP.
+ */
+int rlbm_device_copy(void* dst, const void* src, size_t bytes, int workgroups, void* stream);
 
 /* Last error message of ctx (or of the last failed context-less call when
  * ctx is NULL).  The string is owned by the library. */

@@ -98,10 +98,13 @@ def positive_window(bases, mbar, lo, hi, grid=60, zoom=12, dps=40):
             return inside
 
         step = (c - a) / grid
+        # (the bound is checked before the weights: beyond v_max the
+        # abscissae are not real)
         left = best
-        while min_weight(bases, mbar, left - step, dps) > 0 and left - step > lo:
+        while left - step > lo and min_weight(bases, mbar, left - step, dps) > 0:
             left -= step
         right = best
-        while min_weight(bases, mbar, right + step, dps) > 0 and right + step < hi:
+        while right + step < hi and min_weight(bases, mbar, right + step, dps) > 0:
             right += step
-        return edge(left, left - step), edge(right, right + step), best
+        # (a window that reaches the search interval's end is cut there)
+        return edge(left, max(left - step, mpf(lo))), edge(right, min(right + step, mpf(hi))), best

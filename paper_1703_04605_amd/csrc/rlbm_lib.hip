@@ -657,16 +657,19 @@ k_step(RlbmStepArgs a) {
 template <typename S>
 __device__ __forceinline__ void store_ghosts3(S* __restrict__ q, const RlbmLayout& L, int x, int y, int z,
                                               unsigned xm, unsigned ym, unsigned zm, S v) {
-  const unsigned zall = (zm << 1) | 1u, yall = (ym << 1) | 1u, xall = (xm << 1) | 1u;
-  for (unsigned mz = zall; mz; mz &= mz - 1) {
-    const int bz = __builtin_ctz(mz);
+  // bit 0: the owner coordinate, bit i + 1: ghost coordinate i (up to 2 x 16
+  // ghosts per axis, so 33 bits)
+  typedef unsigned long long M64;
+  const M64 zall = ((M64)zm << 1) | 1ull, yall = ((M64)ym << 1) | 1ull, xall = ((M64)xm << 1) | 1ull;
+  for (M64 mz = zall; mz; mz &= mz - 1) {
+    const int bz = __builtin_ctzll(mz);
     const int cz = bz == 0 ? z : ghost_coord(bz - 1, L.nz, L.Sz);
-    for (unsigned my = yall; my; my &= my - 1) {
-      const int by = __builtin_ctz(my);
+    for (M64 my = yall; my; my &= my - 1) {
+      const int by = __builtin_ctzll(my);
       const int cy = by == 0 ? y : ghost_coord(by - 1, L.ny, L.Sy);
       const long long row = (long long)(cz + L.GZ) * L.zs + (long long)(cy + L.GY) * L.rs + L.GX;
-      for (unsigned mx = xall; mx; mx &= mx - 1) {
-        const int bx = __builtin_ctz(mx);
+      for (M64 mx = xall; mx; mx &= mx - 1) {
+        const int bx = __builtin_ctzll(mx);
         if (bx == 0 && by == 0 && bz == 0) continue;
         const int cx = bx == 0 ? x : ghost_coord(bx - 1, L.nx, L.Sx);
         q[row + cx] = v;
@@ -676,6 +679,11 @@ __device__ __forceinline__ void store_ghosts3(S* __restrict__ q, const RlbmLayou
 }
 
 template <int P> struct Rows3;
+static_assert(RLBM_ROW3 * sizeof(float) % 16 == 0 && RLBM_ROWM3 * sizeof(float) % 16 == 0,
+              "3D table rows must be whole 16-byte structs");
+static_assert(RLBM_ROWF * sizeof(float) % 16 == 0 && RLBM_ROWMF * sizeof(float) % 16 == 0 &&
+                  RLBM_ROWD * sizeof(double) % 16 == 0 && RLBM_ROWMD * sizeof(double) % 16 == 0,
+              "2D table rows must be whole 16-byte structs");
 template <> struct Rows3<RLBM_FP64> {
   struct alignas(16) M { double v[RLBM_ROWM3]; };
   struct alignas(16) E { double v[RLBM_ROW3]; };
@@ -1056,6 +1064,24 @@ StepFn select_step(int prec, int Q, bool guess) {
   }
 }
 
+// 3D step kernels by class count (every population of the stencil is a class)
+template <int P>
+StepFn step3_kernel(int Q) {
+  if (Q <= 48) return k_step3<48, 1, P>;
+  if (Q <= 57) return k_step3<57, 49, P>;
+  if (Q <= 73) return k_step3<73, 58, P>;
+  if (Q <= 96) return k_step3<96, 74, P>;
+  return k_step3<160, 97, P>;
+}
+
+StepFn select_step3(int prec, int Q) {
+  switch (prec) {
+    case RLBM_FP64: return step3_kernel<RLBM_FP64>(Q);
+    case RLBM_FP32_DEV: return step3_kernel<RLBM_FP32_DEV>(Q);
+    default: return step3_kernel<RLBM_FP16_DEV>(Q);
+  }
+}
+
 // Diagnostic: the network's guess (eps, ux, uy) for the current state, from the
 // same in-kernel inference as the step (one wave per 64 consecutive sites).
 __global__ void __launch_bounds__(kBlock) k_guess(RlbmStepArgs a, float* __restrict__ out) {
@@ -1365,19 +1391,24 @@ __global__ void __launch_bounds__(kBlock) k_fields_setup(RlbmOffsetsArg o, RlbmT
 // use_static the health slots live in the device's static array and nothing
 // is allocated.
 static int init_fields_impl(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n, const double* T,
-                            const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
-                            void* stream, bool use_static) {
+                            const double* ux, const double* uy, const double* uz, void* popA, void* popB,
+                            size_t pop_bytes, void* stream, bool use_static, bool three_d) {
   if (!c || !lat) return fail(c, RLBM_EINVAL, "NULL context or lattice");
   const RlbmConsts& k = c->h_tab->c;
+  if ((k.dim == 3) != three_d)
+    return fail(c, RLBM_EINVAL, "%s", three_d ? "rlbm_init_fields3 needs a 3D stencil (dim 3)"
+                                              : "3D stencils take rlbm_init_fields3");
   RlbmLayout L;
   RlbmOffsetsArg offs;
   if (const char* why = check_lattice(*c->h_tab, lat, L, offs.v)) return fail(c, RLBM_EINVAL, "%s", why);
-  if (!n || !T || !ux || !uy || !popA || !popB || popA == popB)
+  if (!n || !T || !ux || !uy || (three_d && !uz) || !popA || !popB || popA == popB)
     return fail(c, RLBM_EINVAL, "NULL field or population buffer");
-  const size_t need = rlbm_population_bytes(c, lat->nx, lat->ny);
+  const int nz = three_d ? lat->nz : 1;
+  const size_t need = three_d ? rlbm_population_bytes3(c, lat->nx, lat->ny, nz)
+                              : rlbm_population_bytes(c, lat->nx, lat->ny);
   if (pop_bytes < need) return fail(c, RLBM_EINVAL, "population buffer too small");
   const int tiles_x = (lat->nx + kWave - 1) / kWave;
-  const long long ntiles = (long long)tiles_x * lat->ny;
+  const long long ntiles = (long long)tiles_x * lat->ny * nz;
   if (use_static && ntiles > kStaticSlots)
     return fail(c, RLBM_EINVAL, "%s",
                 "lattice too large for the allocation-free set-up (more than 262144 tiles of 64 sites of a row)");
@@ -1444,12 +1475,20 @@ static int init_fields_impl(rlbm_ctx* c, const rlbm_lattice_desc* lat, const dou
   ia.L = c->L;
   ia.n = n; ia.T = T; ia.ux = ux; ia.uy = uy;
   ia.tab = c->d_tab;
-  long long sites = (long long)lat->nx * lat->ny;
+  long long sites = (long long)lat->nx * lat->ny * nz;
   dim3 grid((unsigned)((sites + kBlock - 1) / kBlock));
-  switch (k.precision) {
-    case RLBM_FP64: hipLaunchKernelGGL(k_init<RLBM_FP64>, grid, dim3(kBlock), 0, s, ia); break;
-    case RLBM_FP32_DEV: hipLaunchKernelGGL(k_init<RLBM_FP32_DEV>, grid, dim3(kBlock), 0, s, ia); break;
-    default: hipLaunchKernelGGL(k_init<RLBM_FP16_DEV>, grid, dim3(kBlock), 0, s, ia); break;
+  if (three_d) {
+    switch (k.precision) {
+      case RLBM_FP64: hipLaunchKernelGGL(k_init3<RLBM_FP64>, grid, dim3(kBlock), 0, s, ia, uz); break;
+      case RLBM_FP32_DEV: hipLaunchKernelGGL(k_init3<RLBM_FP32_DEV>, grid, dim3(kBlock), 0, s, ia, uz); break;
+      default: hipLaunchKernelGGL(k_init3<RLBM_FP16_DEV>, grid, dim3(kBlock), 0, s, ia, uz); break;
+    }
+  } else {
+    switch (k.precision) {
+      case RLBM_FP64: hipLaunchKernelGGL(k_init<RLBM_FP64>, grid, dim3(kBlock), 0, s, ia); break;
+      case RLBM_FP32_DEV: hipLaunchKernelGGL(k_init<RLBM_FP32_DEV>, grid, dim3(kBlock), 0, s, ia); break;
+      default: hipLaunchKernelGGL(k_init<RLBM_FP16_DEV>, grid, dim3(kBlock), 0, s, ia); break;
+    }
   }
   HIPCHECK(c, hipGetLastError());
   c->have_fields = true;
@@ -1459,13 +1498,19 @@ static int init_fields_impl(rlbm_ctx* c, const rlbm_lattice_desc* lat, const dou
 extern "C" int rlbm_init_fields(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n, const double* T,
                                 const double* ux, const double* uy, void* popA, void* popB, size_t pop_bytes,
                                 void* stream) {
-  return init_fields_impl(c, lat, n, T, ux, uy, popA, popB, pop_bytes, stream, false);
+  return init_fields_impl(c, lat, n, T, ux, uy, nullptr, popA, popB, pop_bytes, stream, false, false);
+}
+
+extern "C" int rlbm_init_fields3(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n, const double* T,
+                                 const double* ux, const double* uy, const double* uz, void* popA, void* popB,
+                                 size_t pop_bytes, void* stream) {
+  return init_fields_impl(c, lat, n, T, ux, uy, uz, popA, popB, pop_bytes, stream, false, true);
 }
 
 extern "C" int rlbm_init_fields_noalloc(rlbm_ctx* c, const rlbm_lattice_desc* lat, const double* n,
                                         const double* T, const double* ux, const double* uy, void* popA,
                                         void* popB, size_t pop_bytes, void* stream) {
-  return init_fields_impl(c, lat, n, T, ux, uy, popA, popB, pop_bytes, stream, true);
+  return init_fields_impl(c, lat, n, T, ux, uy, nullptr, popA, popB, pop_bytes, stream, true, false);
 }
 
 extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
@@ -1492,14 +1537,15 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
     for (int i = 0; i < 24; ++i) a.mlp_norm[i] = c->guess->h_norm[i];
     for (int i = 0; i < 9; ++i) a.mlp_norm[9 + i] = 1.0f / c->guess->h_norm[9 + i];
   }
-  StepFn fn = (c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? fixed_step(c->fixed_id, g) : nullptr;
-  if (!fn) fn = select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
+  const bool d3 = c->h_tab->c.dim == 3;
+  StepFn fn = (!d3 && c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? fixed_step(c->fixed_id, g) : nullptr;
+  if (!fn) fn = d3 ? select_step3(c->h_tab->c.precision, c->h_tab->c.Q) : select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
   if (!fn) return fail(c, RLBM_ESTATE, "no step kernel for this stencil");
   a.tiles_x = c->tiles_x;
   a.ntiles = c->ntiles;
   // byte offsets as in the offset table (range-checked below 2^31 there)
   const long long es = c->h_tab->c.precision == RLBM_FP64 ? 8 : c->h_tab->c.precision == RLBM_FP32_DEV ? 4 : 2;
-  a.fo_base = (unsigned)(es * ((long long)c->L.Sy * c->L.rs + c->L.Sx));
+  a.fo_base = (unsigned)(es * ((long long)c->L.Sz * c->L.zs + (long long)c->L.Sy * c->L.rs + c->L.Sx));
   a.fo_cs = (unsigned)(es * c->L.cs);
   const unsigned nwg = (unsigned)((c->ntiles + kStepBlock / kWave - 1) / (kStepBlock / kWave));
   // class offsets of this lattice, in the context's device table
@@ -1523,9 +1569,36 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   return RLBM_OK;
 }
 
+extern "C" int rlbm_moments3(rlbm_ctx* c, double* n, double* eps, double* T, double* P, double* ux, double* uy,
+                             double* uz, double* raw14, void* stream) {
+  if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
+  if (c->h_tab->c.dim != 3) return fail(c, RLBM_EINVAL, "rlbm_moments3 needs a 3D stencil");
+  if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_moments3 before rlbm_init_fields3");
+  RlbmMomArgs a;
+  a.src = c->buf[c->cur];
+  a.L = c->L;
+  a.shift = c->shifted;
+  a.landau_tol = c->lat.landau_tol;
+  a.landau_maxit = c->lat.landau_maxit;
+  a.landau_method = c->lat.landau_method;
+  a.tab = c->d_tab;
+  a.n = n; a.eps = eps; a.T = T; a.P = P; a.ux = ux; a.uy = uy; a.raw9 = nullptr;
+  long long sites = (long long)a.L.nx * a.L.ny * a.L.nz;
+  dim3 grid((unsigned)((sites + kBlock - 1) / kBlock));
+  hipStream_t s = (hipStream_t)stream;
+  switch (c->h_tab->c.precision) {
+    case RLBM_FP64: hipLaunchKernelGGL(k_moments3<RLBM_FP64>, grid, dim3(kBlock), 0, s, a, uz, raw14); break;
+    case RLBM_FP32_DEV: hipLaunchKernelGGL(k_moments3<RLBM_FP32_DEV>, grid, dim3(kBlock), 0, s, a, uz, raw14); break;
+    default: hipLaunchKernelGGL(k_moments3<RLBM_FP16_DEV>, grid, dim3(kBlock), 0, s, a, uz, raw14); break;
+  }
+  HIPCHECK(c, hipGetLastError());
+  return RLBM_OK;
+}
+
 extern "C" int rlbm_moments(rlbm_ctx* c, double* n, double* eps, double* T, double* P, double* ux, double* uy,
                             double* raw9, void* stream) {
   if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
+  if (c->h_tab->c.dim == 3) return fail(c, RLBM_EINVAL, "3D stencils take rlbm_moments3");
   if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_moments before rlbm_init_fields");
   RlbmMomArgs a;
   a.src = c->buf[c->cur];
@@ -1614,8 +1687,8 @@ extern "C" const char* rlbm_last_error(const rlbm_ctx* c) { return c ? c->err : 
 
 extern "C" int rlbm_set_landau_guess(rlbm_ctx* c, const rlbm_mlp* m) {
   if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
-  if (m && c->h_tab->c.precision != RLBM_FP32_DEV)
-    return fail(c, RLBM_EINVAL, "the learned guess is available for float32 deviation storage");
+  if (m && (c->h_tab->c.precision != RLBM_FP32_DEV || c->h_tab->c.dim == 3))
+    return fail(c, RLBM_EINVAL, "the learned guess is available for float32 deviation storage in 1D and 2D");
   if (m && c->warm) return fail(c, RLBM_EINVAL, "the learned guess and the warm start are exclusive");
   c->guess = m;
   return RLBM_OK;
@@ -1629,6 +1702,7 @@ extern "C" int rlbm_set_warm_start(rlbm_ctx* c, int enable) {
   }
   if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_set_warm_start before rlbm_init_fields");
   if (c->guess) return fail(c, RLBM_EINVAL, "the learned guess and the warm start are exclusive");
+  if (c->h_tab->c.dim == 3) return fail(c, RLBM_EINVAL, "the warm start is available in 1D and 2D");
   const size_t need = (size_t)3 * c->L.nx * c->L.ny;
   if (c->warm_cap < need) {
     if (c->d_warm) HIPCHECK(c, hipFree(c->d_warm));
@@ -1660,6 +1734,53 @@ extern "C" int rlbm_landau_guess_fields(rlbm_ctx* c, float* out, void* stream) {
   hipLaunchKernelGGL(k_guess, dim3((unsigned)((sites + kBlock - 1) / kBlock)), dim3(kBlock), 0, (hipStream_t)stream,
                      a, out);
   HIPCHECK(c, hipGetLastError());
+  return RLBM_OK;
+}
+
+// ====================================================================== copy ceiling
+//
+// A plain streaming copy (16-byte loads and stores, several in flight per
+// lane, a grid of a few waves per SIMD striding over the buffer): the
+// achievable HBM rate that the step kernels' traffic is compared with.
+
+namespace rlbm {
+constexpr int kCopyBlock = 256;
+constexpr int kCopyUnroll = 4;
+
+typedef unsigned U32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(kCopyBlock) k_copy(U32x4* __restrict__ dst, const U32x4* __restrict__ src,
+                                                     long long n16) {
+  const long long stride = (long long)gridDim.x * kCopyBlock * kCopyUnroll;
+  for (long long i = ((long long)blockIdx.x * kCopyBlock * kCopyUnroll) + threadIdx.x; i < n16; i += stride) {
+    U32x4 v[kCopyUnroll];
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const long long k = i + (long long)u * kCopyBlock;
+      if (k < n16) v[u] = __builtin_nontemporal_load(src + k);
+    }
+#pragma unroll
+    for (int u = 0; u < kCopyUnroll; ++u) {
+      const long long k = i + (long long)u * kCopyBlock;
+      if (k < n16) __builtin_nontemporal_store(v[u], dst + k);
+    }
+  }
+}
+}  // namespace rlbm
+
+extern "C" int rlbm_device_copy(void* dst, const void* src, size_t bytes, int workgroups, void* stream) {
+  if (!dst || !src || bytes % 16 != 0 || workgroups <= 0) {
+    rlbm_set_global_error("rlbm_device_copy: NULL buffer, size not a multiple of 16 bytes or no workgroups");
+    return RLBM_EINVAL;
+  }
+  if (bytes == 0) return RLBM_OK;
+  hipLaunchKernelGGL(k_copy, dim3((unsigned)workgroups), dim3(kCopyBlock), 0, (hipStream_t)stream, (U32x4*)dst,
+                     (const U32x4*)src, (long long)(bytes / 16));
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    rlbm_set_global_error(hipGetErrorString(e));
+    return RLBM_EHIP;
+  }
   return RLBM_OK;
 }
 

@@ -24,11 +24,12 @@ enum { RLBM_R_NX = 10, RLBM_R_NY = 11, RLBM_R_INVSCALE = 12 };
 
 // 3D lattices: all 14 second-order polynomials (Appendix A order 0, 1_0,
 // 1_x, 1_y, 1_z, 2_00, 2_0x, 2_0y, 2_0z, 2_xx, 2_yy, 2_xz, 2_yz, 2_xy);
-// equilibrium rows [M_j0 .. M_j13, n_x, n_y, n_z, 1/scale], moment rows
+// equilibrium rows [M_j0 .. M_j13, n_x, n_y, n_z, 1/scale, 0, 0], moment rows
 // [p0, px, py, pz, p0p0, p0px, p0py, p0pz, pxpx, pxpy, pxpz, pypy, pypz,
-// pzpz, scale, 0]
+// pzpz, scale, 0].  Row lengths keep every row a multiple of 16 bytes (the
+// kernels read a row as one 16-byte aligned struct).
 #define RLBM_NB3 14
-#define RLBM_ROW3 18
+#define RLBM_ROW3 20
 #define RLBM_ROWM3 16
 enum { RLBM_R3_NX = 14, RLBM_R3_NY = 15, RLBM_R3_NZ = 16, RLBM_R3_INVSCALE = 17 };
 #define RLBM_RM3_SCALE 14

@@ -35,7 +35,8 @@ EXPORTS = ["rlbm_init_stencil", "rlbm_solve_stencil", "rlbm_class_table", "rlbm_
            "rlbm_landau_guess_fields", "rlbm_batch_create", "rlbm_batch_destroy", "rlbm_batch_population_bytes",
            "rlbm_batch_sites", "rlbm_batch_init", "rlbm_batch_step_persistent", "rlbm_batch_moments",
            "rlbm_batch_get_health", "rlbm_set_step_variant", "rlbm_step_kernel", "rlbm_check_lattice",
-           "rlbm_init_fields_noalloc", "rlbm_batch_occupancy"]
+           "rlbm_init_fields_noalloc", "rlbm_batch_occupancy", "rlbm_population_bytes3", "rlbm_init_fields3",
+           "rlbm_moments3", "rlbm_device_copy"]
 
 STEP_AUTO, STEP_TABLE, STEP_FIXED = 0, 1, 2
 
@@ -96,6 +97,11 @@ def lib():
     L.rlbm_init_fields_noalloc.argtypes = [vp, ctypes.POINTER(LatticeDesc), vp, vp, vp, vp, vp, vp,
                                            ctypes.c_size_t, vp]
     L.rlbm_check_lattice.argtypes = [ctypes.POINTER(StencilDesc), ctypes.POINTER(LatticeDesc)]
+    L.rlbm_population_bytes3.argtypes = [vp, ci, ci, ci]
+    L.rlbm_population_bytes3.restype = ctypes.c_size_t
+    L.rlbm_init_fields3.argtypes = [vp, ctypes.POINTER(LatticeDesc), vp, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp]
+    L.rlbm_moments3.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.rlbm_device_copy.argtypes = [vp, vp, ctypes.c_size_t, ci, vp]
     L.rlbm_step.argtypes = [vp, ci, vp]
     L.rlbm_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.rlbm_get_health.argtypes = [vp, ctypes.POINTER(ctypes.c_uint), ctypes.POINTER(ctypes.c_ulonglong),
@@ -390,6 +396,59 @@ class Solver:
         dt = {"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.float16}[self.precision]
         buf = self.pop[0] if (self.step_count() % 2 == 0) else self.pop[1]
         return buf.view(dt)
+
+
+def device_copy(dst, src, workgroups=2048):
+    """Streaming copy of src into dst (CUDA tensors of equal byte size, a
+    multiple of 16) on the current stream."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    _check(lib().rlbm_device_copy(dst.data_ptr(), src.data_ptr(), nbytes, int(workgroups),
+                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+
+
+class Solver3D(Solver):
+    """A 3D lattice (Nx x Ny x Nz, every population of the stencil) on the
+    current device; fields are CUDA float64 tensors [nz, ny, nx]."""
+
+    def __init__(self, bases, zeta, v0, precision="fp64", n_ref=1.0, T_ref=1.0, v0_lo=0.0, v0_hi=0.0):
+        super().__init__(bases, zeta, v0, dim=3, precision=precision, n_ref=n_ref, T_ref=T_ref, v0_lo=v0_lo,
+                         v0_hi=v0_hi)
+        self.nz = None
+
+    def population_bytes3(self, nx, ny, nz):
+        return lib().rlbm_population_bytes3(self.ctx, nx, ny, nz)
+
+    def init_fields(self, n, T, ux, uy, uz, bc=("periodic", "periodic", "periodic"), tau=1.0, landau_tol=0.0,
+                    landau_maxit=0):
+        torch = self.torch
+        nz, ny, nx = n.shape
+        for a in (n, T, ux, uy, uz):
+            assert a.is_cuda and a.dtype == torch.float64 and a.is_contiguous() and tuple(a.shape) == (nz, ny, nx)
+        lat = lattice_desc(nx, ny, bc[:2], tau, landau_tol, landau_maxit, "newton")
+        lat.nz = nz
+        lat.bc_z = BC[bc[2]]
+        nbytes = self.population_bytes3(nx, ny, nz)
+        self.pop = [torch.empty(nbytes, dtype=torch.uint8, device=n.device) for _ in range(2)]
+        self._fields = (n, T, ux, uy, uz)
+        _check(lib().rlbm_init_fields3(self.ctx, ctypes.byref(lat), n.data_ptr(), T.data_ptr(), ux.data_ptr(),
+                                       uy.data_ptr(), uz.data_ptr(), self.pop[0].data_ptr(), self.pop[1].data_ptr(),
+                                       nbytes, self._stream()), self.ctx)
+        self.nx, self.ny, self.nz = nx, ny, nz
+
+    def moments(self, raw=False):
+        torch = self.torch
+        dev = self.pop[0].device
+        shp = (self.nz, self.ny, self.nx)
+        out = {k: torch.empty(shp, dtype=torch.float64, device=dev) for k in ("n", "eps", "T", "P", "ux", "uy", "uz")}
+        raw14 = torch.empty((14,) + shp, dtype=torch.float64, device=dev) if raw else None
+        _check(lib().rlbm_moments3(self.ctx, out["n"].data_ptr(), out["eps"].data_ptr(), out["T"].data_ptr(),
+                                   out["P"].data_ptr(), out["ux"].data_ptr(), out["uy"].data_ptr(),
+                                   out["uz"].data_ptr(), raw14.data_ptr() if raw else None, self._stream()), self.ctx)
+        if raw:
+            out["raw14"] = raw14
+        return out
 
 
 class Batch:

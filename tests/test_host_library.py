@@ -150,3 +150,29 @@ def test_lattice_checks_on_the_host():
     rlbm.check_lattice(*args, precision="fp16", nx=4096, ny=8192)
     with pytest.raises(rlbm.RlbmError):
         rlbm.check_lattice(*args, precision="fp16", nx=8192, ny=8192)
+
+
+def test_3d_stencil_and_lattice_checks_on_the_host():
+    """A 3D stencil stores every population (q == q3); 3D lattice
+    descriptions need nz >= 1 and the Newton Landau solve; 2D ones nz 0 or 1."""
+    st = workloads.STENCILS["zeta5"]
+    info = rlbm.solve_stencil(st["bases"], st["zeta"], st["v0"], dim=3)
+    assert info["q"] == info["q3"] == 57
+    d3 = rlbm.make_desc(st["bases"], st["zeta"], st["v0"], 3, "fp32")
+    d2 = rlbm.make_desc(st["bases"], st["zeta"], st["v0"], 2, "fp32")
+    L = rlbm.lib()
+    lat = rlbm.lattice_desc(64, 32)
+    for nz, want3, want2 in ((0, rlbm.RLBM_EINVAL, rlbm.RLBM_OK), (1, rlbm.RLBM_OK, rlbm.RLBM_OK),
+                             (16, rlbm.RLBM_OK, rlbm.RLBM_EINVAL)):
+        lat.nz = nz
+        assert L.rlbm_check_lattice(d3, lat) == want3, nz
+        assert L.rlbm_check_lattice(d2, lat) == want2, nz
+    lat.nz = 16
+    lat.landau_method = rlbm.LANDAU["fixed_point"]
+    assert L.rlbm_check_lattice(d3, lat) == rlbm.RLBM_EINVAL
+    lat.landau_method = rlbm.LANDAU["newton"]
+    lat.bc_z = 3
+    assert L.rlbm_check_lattice(d3, lat) == rlbm.RLBM_EINVAL
+    lat = rlbm.lattice_desc(1024, 1024)
+    lat.nz = 1024          # 2^30 sites but far more than 2^31 stored elements
+    assert L.rlbm_check_lattice(d3, lat) == rlbm.RLBM_EINVAL

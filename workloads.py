@@ -66,6 +66,20 @@ def taylor_green(nx, ny, seed=0, umax=0.3, noise=0.01):
     return n, T, ux, uy
 
 
+def taylor_green_3d(nx, ny, nz, seed=0, umax=0.3, noise=0.01):
+    """Periodic 3D Taylor-Green vortex u = umax (sin x cos y cos z,
+    -cos x sin y cos z, 0) (angles 2 pi x/L) with 1% Gaussian noise on n and
+    T around n = T = 1; arrays [nz, ny, nx]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z, y, x = np.meshgrid(2 * np.pi * (np.arange(nz) + 0.5) / nz, 2 * np.pi * (np.arange(ny) + 0.5) / ny,
+                          2 * np.pi * (np.arange(nx) + 0.5) / nx, indexing="ij")
+    ux = umax * np.sin(x) * np.cos(y) * np.cos(z)
+    uy = -umax * np.cos(x) * np.sin(y) * np.cos(z)
+    n = 1.0 + noise * rng.standard_normal((nz, ny, nx))
+    T = 1.0 + noise * rng.standard_normal((nz, ny, nx))
+    return n, T, ux, uy, np.zeros((nz, ny, nx))
+
+
 def kelvin_helmholtz(nx, ny, seed=0, beta=0.4, width=8.0, amp=0.01):
     """Doubly periodic shear layers at y = L/4, 3L/4 with tanh profile of the
     given width (cells), speed +-beta, and a seeded sinusoidal transverse
@@ -101,18 +115,26 @@ def random_smooth(nx, ny, seed=0, umax=0.3):
     return n, T, ux, uy
 
 
-# Stencils of the batched workload, by mbar band: each band lies inside the
-# stencil's working range (positive weights for some v0), and together they
-# cover [0.36, 10] without a gap:
+# Stencils of the batched workload, by mbar band.  Each band lies inside the
+# stencil's working range (positive weights for some v0), the bands cover
+# [0.36, 10] without a gap, and within each band the stencil is the one whose
+# smallest group weight is largest among the working ones (a stencil near the
+# edge of its range has a nearly vanishing weight and runs strong shocks
+# unstably):
 #   s133: the paper's 133-population stencil (Fig. 6), works on [0.3585, 0.5823]
 #   s46:  46 populations, works on [0.486, 1.185]
+#   s67:  the 67-population mbar = 1 stencil, works on [0.975, 1.064], [1.665, 5.489]
 #   s73:  73 populations, works on [1.025, > 8]
 #   s57:  G1..G6 (57 populations), works on [4.01, > 40]
+_S67 = [(0, 0, 0), (2, 0, 0), (3, 0, 0), (3, 2, 0), (3, 2, 2), (4, 0, 0)]
+_S73 = [(0, 0, 0), (2, 0, 0), (2, 1, 1), (2, 2, 0), (2, 2, 1), (3, 0, 0)]
 BATCH_BANDS = [
     (0.36, 0.52, "s133", [(0, 0, 0), (3, 3, 0), (5, 4, 2), (5, 3, 3), (6, 3, 0), (6, 2, 2)]),
-    (0.52, 1.10, "s46", [(0, 0, 0), (3, 3, 0), (5, 0, 0), (5, 1, 0), (3, 3, 3), (5, 1, 1)]),
-    (1.10, 6.00, "s73", [(0, 0, 0), (2, 0, 0), (2, 1, 1), (2, 2, 0), (2, 2, 1), (3, 0, 0)]),
-    (6.00, 10.0, "s57", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 1), (2, 0, 0), (2, 1, 0)]),
+    (0.52, 0.98, "s46", [(0, 0, 0), (3, 3, 0), (5, 0, 0), (5, 1, 0), (3, 3, 3), (5, 1, 1)]),
+    (0.98, 1.06, "s67", _S67),
+    (1.06, 1.70, "s73", _S73),
+    (1.70, 4.20, "s67", _S67),
+    (4.20, 10.0, "s57", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 1), (2, 0, 0), (2, 1, 0)]),
 ]
 BATCH_ZETA_MIN = 0.36   # no second-order stencil has positive weights much below 0.3585
 
