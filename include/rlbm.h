@@ -109,7 +109,12 @@ typedef struct {
   double v0_lo, v0_hi;   /* positive-weight window found (search only) */
   double weights[16];    /* weight per group (per population of the group) */
   double ortho_residual; /* max |sum_i w_i J_l(p_i) J_k(p_i) - delta_lk| */
-  int max_shift;         /* max |n_x| (and |n_y| in 2D) of the stencil */
+  int max_shift;         /* max |n_x| (and |n_y|, |n_z|) of the stencil */
+  double cond;           /* 2-norm condition number at v0 of the system
+                            matrix of the quadrature problem (Sec. III.D: rows
+                            the pairs l <= k of the 14 polynomials, columns the
+                            groups, entries sum_{i in group} J_l J_k), the
+                            quantity that grows at small mbar */
 } rlbm_stencil_info;
 
 /*

@@ -63,7 +63,12 @@ def weights(bases, mbar, v0, dps=50):
 
 
 def min_weight(bases, mbar, v0, dps=40):
-    w, _ = weights(bases, mbar, v0, dps)
+    """Smallest weight at v0; -inf where A(v0) is singular (no unique
+    weights exist there, so the point cannot carry a quadrature)."""
+    try:
+        w, _ = weights(bases, mbar, v0, dps)
+    except ZeroDivisionError:
+        return mpf("-inf")
     return min(w)
 
 

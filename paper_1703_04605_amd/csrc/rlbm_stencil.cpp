@@ -183,10 +183,10 @@ struct Stencil {
     }
   }
 
-  // the six reduced conditions; returns false if singular
-  bool weights(ld v0, std::vector<ld>& w) const {
-    if (ng != 6) return false;
-    std::vector<ld> a(36), b(6);
+  // the six reduced conditions as a 6 x 6 system a w = b (row-major a)
+  void system(ld v0, std::vector<ld>& a, std::vector<ld>& b) const {
+    a.assign(36, 0.0L);
+    b.assign(6, 0.0L);
     for (int g = 0; g < 6; ++g) {
       ld gam = 1.0L / sqrtl(1.0L - v0 * v0 * n2[g]);
       ld p0 = m * gam;
@@ -203,8 +203,16 @@ struct Stencil {
     }
     for (int r = 0; r < 5; ++r) b[r] = mu[r];
     b[5] = 0.0L;
+  }
+
+  // the six reduced conditions; returns false if singular
+  bool weights(ld v0, std::vector<ld>& w) const {
+    if (ng != 6) return false;
+    std::vector<ld> a, b;
+    system(v0, a, b);
     return solve_dense(6, a, b, w);
   }
+
 
   ld min_weight(ld v0) const {
     std::vector<ld> w;
@@ -226,6 +234,36 @@ struct Stencil {
     }
   }
 };
+
+// Eigenvalues of a symmetric n x n matrix (cyclic Jacobi rotations).
+void jacobi_eigenvalues(int n, std::vector<ld> a, std::vector<ld>& ev) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    ld off = 0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += a[p * n + q] * a[p * n + q];
+    if (off < 1e-60L) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const ld apq = a[p * n + q];
+        if (apq == 0) continue;
+        const ld theta = (a[q * n + q] - a[p * n + p]) / (2 * apq);
+        const ld t = (theta >= 0 ? 1 : -1) / (fabsl(theta) + sqrtl(theta * theta + 1));
+        const ld c = 1 / sqrtl(t * t + 1), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const ld akp = a[k * n + p], akq = a[k * n + q];
+          a[k * n + p] = c * akp - sn * akq;
+          a[k * n + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const ld apk = a[p * n + k], aqk = a[q * n + k];
+          a[p * n + k] = c * apk - sn * aqk;
+          a[q * n + k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  ev.resize(n);
+  for (int i = 0; i < n; ++i) ev[i] = a[i * n + i];
+}
 
 void set_err(char* err, size_t len, const char* msg) {
   if (err && len) snprintf(err, len, "%s", msg);
@@ -384,6 +422,26 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
   ld res = 0;
   for (int l = 0; l < 14; ++l)
     for (int k = 0; k < 14; ++k) res = std::max(res, fabsl(G[l][k] - (l == k ? 1.0L : 0.0L)));
+  // condition number of the system matrix of the quadrature problem at v0
+  // (rows: the pairs l <= k of polynomials, columns: groups, entries
+  // sum over the group's populations of J_l J_k): sqrt of the eigenvalue
+  // ratio of A^T A
+  ld cond = INFINITY;
+  {
+    std::vector<ld> AtA(36, 0.0L);
+    std::vector<ld> row(6);
+    for (int l = 0; l < 14; ++l)
+      for (int k = l; k < 14; ++k) {
+        std::fill(row.begin(), row.end(), 0.0L);
+        for (size_t i = 0; i < pops.size(); ++i) row[pops[i].g] += Jall[i][l] * Jall[i][k];
+        for (int g = 0; g < 6; ++g)
+          for (int h = 0; h < 6; ++h) AtA[g * 6 + h] += row[g] * row[h];
+      }
+    std::vector<ld> ev;
+    jacobi_eigenvalues(6, AtA, ev);
+    const ld mx = *std::max_element(ev.begin(), ev.end()), mn = *std::min_element(ev.begin(), ev.end());
+    if (mn > 0) cond = sqrtl(mx / mn);
+  }
   if (!(res < 1e-10L)) {
     set_err(err, errlen, "orthonormality conditions not satisfied by this group set");
     return RLBM_ENOSTENCIL;
@@ -431,6 +489,7 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
     for (int g = 0; g < 6; ++g) info->weights[g] = (double)w[g];
     info->ortho_residual = (double)res;
     info->max_shift = max_shift;
+    info->cond = (double)cond;
   }
   if (!tab) return RLBM_OK;
 

@@ -58,7 +58,7 @@ class StencilInfo(ctypes.Structure):
     _fields_ = [("q3", ctypes.c_int), ("q", ctypes.c_int), ("v0", ctypes.c_double),
                 ("v0_lo", ctypes.c_double), ("v0_hi", ctypes.c_double),
                 ("weights", ctypes.c_double * 16), ("ortho_residual", ctypes.c_double),
-                ("max_shift", ctypes.c_int)]
+                ("max_shift", ctypes.c_int), ("cond", ctypes.c_double)]
 
 
 class LatticeDesc(ctypes.Structure):
@@ -177,7 +177,7 @@ def check_lattice(bases, zeta, v0, nx, ny, dim=2, precision="fp64", **lattice):
 def info_dict(info):
     return {"q3": info.q3, "q": info.q, "v0": info.v0, "v0_lo": info.v0_lo, "v0_hi": info.v0_hi,
             "weights": [info.weights[i] for i in range(6)], "ortho_residual": info.ortho_residual,
-            "max_shift": info.max_shift}
+            "max_shift": info.max_shift, "cond": info.cond}
 
 
 def solve_stencil(bases, zeta, v0=0.0, dim=2, v0_lo=0.0, v0_hi=0.0):

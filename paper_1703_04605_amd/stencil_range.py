@@ -1,4 +1,5 @@
-"""Working range in mbar = m/T_R of second-order stencils.
+"""Working range in mbar = m/T_R of second-order stencils, and the map of
+Sec. III.D (Fig. 5) over all six-group stencils up to a group size.
 
 A stencil (six velocity groups of App. C) gives a usable quadrature at mbar
 only if the conditions of eq. ortho1 have a solution with all weights
@@ -78,3 +79,95 @@ def search(mbar, max_norm2=18):
         if works(cand, mbar):
             out.append(cand)
     return out
+
+
+def _probe(args):
+    """Working points of one candidate on the mbar grid: for each grid point
+    None, or (populations, v0, min weight, condition number)."""
+    cand, grid = args
+    from paper_1703_04605_amd import rlbm
+    out = []
+    for z in grid:
+        try:
+            i = rlbm.solve_stencil(cand, z)
+            out.append((i["q3"], i["v0"], min(i["weights"][:6]), i["cond"]))
+        except rlbm.RlbmError as e:
+            if e.code != rlbm.RLBM_ENOSTENCIL:
+                raise
+            out.append(None)
+    return cand, out
+
+
+def stencil_map(lo=0.3, hi=40.0, points=36, max_norm2=18, processes=8):
+    """The working-range map of Sec. III.D (Fig. 5) for every six-group
+    stencil {(0,0,0)} + five groups with |n|^2 <= max_norm2, on a logarithmic
+    mbar grid: each stencil that works somewhere, with its working grid
+    points, and per grid point the stencil with the fewest populations (ties:
+    the larger smallest weight) and the condition number of its system
+    matrix at the window's middle."""
+    import itertools
+    from multiprocessing import get_context
+    grid = [lo * (hi / lo) ** (i / (points - 1)) for i in range(points)]
+    cands = [[(0, 0, 0)] + list(c) for c in itertools.combinations(base_vectors(max_norm2), 5)]
+    with get_context("spawn").Pool(processes) as pool:
+        res = pool.map(_probe, [(c, grid) for c in cands], chunksize=16)
+    stencils = []
+    for cand, pts in res:
+        if any(p is not None for p in pts):
+            stencils.append({"bases": cand, "populations": next(p[0] for p in pts if p is not None),
+                             "works": [i for i, p in enumerate(pts) if p is not None],
+                             "cond": [p[3] if p is not None else None for p in pts],
+                             "min_weight": [p[2] if p is not None else None for p in pts]})
+    best = []
+    for i, z in enumerate(grid):
+        ok = [s for s in stencils if i in s["works"]]
+        if not ok:
+            best.append(None)
+            continue
+        s = min(ok, key=lambda s: (s["populations"], -s["min_weight"][i]))
+        best.append({"mbar": z, "bases": s["bases"], "populations": s["populations"], "cond": s["cond"][i],
+                     "min_weight": s["min_weight"][i], "working_stencils": len(ok)})
+    return {"grid": grid, "max_norm2": max_norm2, "candidates": len(cands), "stencils": stencils,
+            "smallest_per_point": best}
+
+
+def compact(m):
+    """A compact form of ``stencil_map``'s result for storage: per grid point
+    the number of working stencils, the smallest and the median condition
+    number among them and the smallest stencil; per working stencil its base
+    vectors (as digit strings), population count and working runs of grid
+    indices [first, last]."""
+    import statistics
+    points = []
+    for i, z in enumerate(m["grid"]):
+        conds = sorted(s["cond"][i] for s in m["stencils"] if s["cond"][i] is not None)
+        points.append({"mbar": z, "working": len(conds),
+                       "cond_min": conds[0] if conds else None,
+                       "cond_median": statistics.median(conds) if conds else None,
+                       "smallest": m["smallest_per_point"][i]})
+    stencils = []
+    for s in m["stencils"]:
+        runs, start, prev = [], None, None
+        for i in s["works"]:
+            if start is None:
+                start = i
+            elif i != prev + 1:
+                runs.append([start, prev])
+                start = i
+            prev = i
+        runs.append([start, prev])
+        stencils.append(["".join(str(c) for c in b) for b in s["bases"]] + [s["populations"], runs])
+    return {"grid": m["grid"], "max_norm2": m["max_norm2"], "candidates": m["candidates"],
+            "points": points, "stencils": stencils}
+
+
+if __name__ == "__main__":
+    import json
+    import os
+    import sys
+    n2 = int(sys.argv[1]) if len(sys.argv) > 1 else 18
+    m = stencil_map(max_norm2=n2, processes=int(os.environ.get("RLBM_MAP_PROCESSES", "8")))
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"stencil_map_n{n2}.json")
+    with open(path, "w") as fh:
+        json.dump(compact(m), fh, separators=(",", ":"))
+    print(f"{len(m['stencils'])} of {m['candidates']} stencils work somewhere on the grid; written to {path}")

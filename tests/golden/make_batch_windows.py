@@ -25,7 +25,9 @@ def main():
     problems, _ = workloads.batched_riemann(nprob=8, seed=4, lmax=512)
     out = []
     for i, p in enumerate(problems):
-        w = quad.positive_window(p["bases"], p["zeta"], 1e-4, vmax(p["bases"]) * (1 - 1e-9))
+        # a grid fine enough to resolve windows 0.2% of the interval wide
+        # (the window holding the largest min_k w_k is the one used)
+        w = quad.positive_window(p["bases"], p["zeta"], 1e-4, vmax(p["bases"]) * (1 - 1e-9), grid=600)
         if w is None:
             raise SystemExit(f"no positive window for problem {i} (mbar {p['zeta']})")
         lo, hi, best = (float(x) for x in w)

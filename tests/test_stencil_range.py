@@ -97,3 +97,52 @@ def test_library_windows_match_oracle_windows_of_the_batch_subset():
         assert abs(info["v0_lo"] - w["v0_lo"]) < 1e-6 * width + 1e-13, w
         assert abs(info["v0_hi"] - w["v0_hi"]) < 1e-6 * width + 1e-13, w
         assert w["v0_lo"] < info["v0"] < w["v0_hi"]
+
+
+@pytest.mark.parametrize("name", ["zeta5", "zeta036"])
+def test_condition_number_matches_oracle_system(name):
+    """The library's condition number of the quadrature problem's system
+    matrix (Sec. III.D) equals the ratio of the extreme singular values of
+    the oracle's own A(v0) (mpmath, all 105 pair conditions)."""
+    from mpmath import mp
+    from oracle import quadrature as quad
+    from paper_1703_04605_amd import rlbm
+    st = workloads.STENCILS[name]
+    info = rlbm.solve_stencil(st["bases"], st["zeta"], st["v0"])
+    with mp.workdps(40):
+        A, _ = quad.system(st["bases"], st["zeta"], st["v0"], dps=40)
+        sv = mp.svd_r(A, compute_uv=False)
+        cond = float(max(sv) / min(sv))
+    assert abs(info["cond"] - cond) < 1e-9 * cond, (info["cond"], cond)
+
+
+def test_stored_map_against_oracle():
+    """Sampled entries of the stored working-range map (all six-group
+    stencils with |n|^2 <= 18, written by stencil_range.stencil_map): where
+    the map says a stencil works, the oracle's weights at the library's v0
+    are all positive; at the grid point just below the smallest working mass
+    the oracle's own window search finds no positive window for the stencil
+    that works at that smallest mass."""
+    import json
+    import os
+    import random
+    from paper_1703_04605_amd import rlbm
+    path = os.path.join(os.path.dirname(sr.__file__), "stencil_map_n18.json")
+    m = json.load(open(path))
+    grid = m["grid"]
+    vec = lambda s: tuple(int(c) for c in s)
+    rng = random.Random(5)
+    picks = [(p["smallest"]["bases"], p["mbar"]) for p in m["points"] if p["smallest"]][::6]
+    for s in rng.sample(m["stencils"], 4):
+        run = s[7][0]
+        picks.append(([vec(b) for b in s[:6]], grid[rng.randint(run[0], run[1])]))
+    for bases, z in picks:
+        bases = [tuple(b) for b in bases]
+        info = rlbm.solve_stencil(bases, z)
+        w, res = quad.weights(bases, z, info["v0"], dps=30)
+        assert min(w) > 0 and res < 1e-20, (bases, z)
+    first = next(i for i, p in enumerate(m["points"]) if p["working"])
+    bases = [tuple(b) for b in m["points"][first]["smallest"]["bases"]]
+    vmax = 1.0 / max(sum(c * c for c in b) for b in bases) ** 0.5
+    assert quad.positive_window(bases, grid[first - 1], 0.02, vmax * (1 - 1e-9), grid=60, zoom=10, dps=30) is None
+    assert not sr.works(bases, grid[first - 1])
