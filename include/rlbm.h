@@ -70,7 +70,9 @@ extern "C" {
 #define RLBM_H_SUPERLUMINAL 4u /* |u| >= 1 */
 #define RLBM_H_RANGE 8u        /* n <= 0, eps <= 0 or eps/n below the rest mass */
 #define RLBM_H_EOS 16u         /* EOS Newton iteration hit its cap */
-#define RLBM_H_FATAL (RLBM_H_NAN | RLBM_H_SUPERLUMINAL | RLBM_H_RANGE)
+#define RLBM_H_SYNC 32u        /* batched launch: a wait on neighbouring tiles timed out,
+                                  or the tiles of one problem did not share one L2 */
+#define RLBM_H_FATAL (RLBM_H_NAN | RLBM_H_SUPERLUMINAL | RLBM_H_RANGE | RLBM_H_SYNC)
 
 typedef struct rlbm_ctx rlbm_ctx;
 
@@ -81,7 +83,10 @@ typedef struct rlbm_ctx rlbm_ctx;
  * p_{i,k} = zeta gamma_k (1, v0 n_{i,k}) (eq. four-momentum); one weight per
  * group solves the second-order orthonormality conditions (eq. ortho1),
  * which for full-symmetric groups reduce to six: the energy moments of
- * order 0..4 of the weight function and one quartic-isotropy condition.
+ * order 0..4 of the weight function and one quartic-isotropy condition.  At
+ * third order (Sec. III.D: eleven independent conditions) they are the
+ * energy moments of order 0..6, the quartic isotropy times p0^0..2 and the
+ * sextic one (p_x^2 p_y^2 p_z^2).
  */
 typedef struct {
   int dim;               /* 2: Nx x Ny lattice (1 x Nx x Ny slab of the 3D
@@ -89,7 +94,7 @@ typedef struct {
                             lattice with every population of the stencil
                             (Sec. V); 3D lattices take rlbm_init_fields3 and
                             rlbm_moments3 */
-  int n_groups;          /* number of groups, 6 at second order */
+  int n_groups;          /* number of groups: 6 at second order, 11 at third */
   const int* group_base; /* host, 3*n_groups ints: base vectors (a, b, c) */
   double zeta;           /* mbar = m / T_R, > 0 */
   double v0;             /* > 0: use this v0 (must give positive weights);
@@ -99,6 +104,17 @@ typedef struct {
   int precision;         /* RLBM_FP64 | RLBM_FP32_DEV | RLBM_FP16_DEV */
   double n_ref, T_ref;   /* deviation reference f^ref = f^eq(n_ref, T_ref, u=0)
                             (ignored for RLBM_FP64; 0 means 1) */
+  int order;             /* expansion order of the equilibrium (eq.
+                            mj-projected-distribution): 0 or 2 = second order
+                            (14 polynomials, 6 groups); 3 = third order (30
+                            polynomials, 11 groups, Sec. III.A and III.D),
+                            RLBM_FP64 only; third-order contexts of every dim
+                            take rlbm_init_fields3 / rlbm_moments3 (nz = 1 for
+                            dim 1 and 2, ny = 1 for dim 1) */
+  const double* weights; /* host, nullable: n_groups weights (per population
+                            of each group) to use instead of solving; needs
+                            v0 > 0, and must pass the same positivity and
+                            orthonormality checks */
 } rlbm_stencil_desc;
 
 typedef struct {
@@ -112,9 +128,10 @@ typedef struct {
   int max_shift;         /* max |n_x| (and |n_y|, |n_z|) of the stencil */
   double cond;           /* 2-norm condition number at v0 of the system
                             matrix of the quadrature problem (Sec. III.D: rows
-                            the pairs l <= k of the 14 polynomials, columns the
-                            groups, entries sum_{i in group} J_l J_k), the
-                            quantity that grows at small mbar */
+                            the pairs l <= k of the 14 (third order: 30)
+                            polynomials, columns the groups, entries
+                            sum_{i in group} J_l J_k), the quantity that grows
+                            at small mbar */
 } rlbm_stencil_info;
 
 /*
@@ -367,8 +384,13 @@ int rlbm_set_warm_start(rlbm_ctx* ctx, int enable);
  * stencil contexts (rlbm_init_stencil with dim 1, RLBM_FP32_DEV, at most 24
  * classes; they must outlive the batch).  The sites of all problems are cut
  * into tiles of 64 sites, one wave each; a cooperative launch spread over the
- * whole device advances every tile through all steps of a call, with a
- * grid-wide barrier between steps.
+ * whole device advances every tile through all steps of a call.  There is
+ * no grid-wide barrier between steps: a tile starts step t once its two
+ * neighbours in the same problem have finished step t - 1 (streaming reaches
+ * at most max |n_x| < 64 sites), and every problem is kept on one L2 (one
+ * XCD) so that this hand-over needs no device-wide cache maintenance.  A
+ * wait that does not end, or tiles of one problem found on two L2s, raise
+ * RLBM_H_SYNC (fatal) and end the launch early.
  */
 typedef struct {
   int nx;                 /* sites */

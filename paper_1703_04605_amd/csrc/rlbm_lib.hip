@@ -1810,9 +1810,21 @@ struct RlbmBatchProblem {
 };
 
 struct RlbmBatchTile {
-  int prob;  // problem index
-  int x0;    // first site of the tile
+  int prob;         // problem index
+  int x0;           // first site of the tile
+  int left, right;  // neighbouring tiles of the same problem, -1 at its ends
 };
+
+// Batched tiles are dealt to the device's L2 domains (XCDs): every tile of a
+// problem goes to one XCD, and each wave takes the tiles of the XCD it runs
+// on.  kBatchXcds bins (the XCD count of the device); the wave's hardware XCC
+// id picks its bin.
+constexpr int kBatchXcds = 8;
+constexpr int kSyncCount = 0;                  // [kBatchXcds] waves registered per bin
+constexpr int kSyncMask = kBatchXcds;          // [kBatchXcds] XCC ids seen per bin (bit mask)
+constexpr int kSyncAbort = 2 * kBatchXcds;     // set when a wave gives up
+constexpr int kSyncDone = 2 * kBatchXcds + 1;  // [ntiles] steps completed per tile
+constexpr unsigned kSpinLimit = 1u << 20;      // ~100 ms of polling per wait
 
 struct RlbmBatchArgs {
   const void* src;
@@ -1829,6 +1841,9 @@ struct RlbmBatchArgs {
   double landau_tol;
   int landau_maxit;
   RlbmSlot* slots;      // one per wave of the grid
+  unsigned* sync;       // kSyncDone + ntiles words, zero at launch
+  const int* xtiles;    // tile indices grouped by XCD bin
+  int xoff[kBatchXcds + 1];
 };
 
 // One site of one problem: pull, moments (float32 rows plus their rounding
@@ -1900,20 +1915,75 @@ __device__ __forceinline__ void batch_site(const RlbmBatchArgs& a, const RlbmBat
   }
 }
 
+__device__ __forceinline__ unsigned sync_load(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Lane 0 polls until both neighbours have completed `need` steps (a missing
+// neighbour counts as done); false when the wait was abandoned.
+__device__ __forceinline__ bool wait_neighbours(const unsigned* sync, int left, int right, unsigned need) {
+  const unsigned* done = sync + kSyncDone;
+  int ok = 1;
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    unsigned spins = 0;
+    while ((left >= 0 && sync_load(done + left) < need) || (right >= 0 && sync_load(done + right) < need)) {
+      if (++spins >= kSpinLimit || ((spins & 255u) == 0 && sync_load(sync + kSyncAbort) != 0)) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  return __shfl(ok, 0) != 0;
+}
+
 __global__ void __launch_bounds__(kBatchBlock) k_batch(RlbmBatchArgs a) {
   namespace cg = cooperative_groups;
   cg::grid_group grid = cg::this_grid();
   const int lane = (int)threadIdx.x & (kWave - 1);
   const int wave = (int)blockIdx.x * (kBatchBlock / kWave) + (int)(threadIdx.x >> 6);
-  const int nwaves = (int)gridDim.x * (kBatchBlock / kWave);
+  unsigned* sync = a.sync;
+  // register with the L2 domain (XCD) this wave runs on
+  const unsigned xcc = __builtin_amdgcn_s_getreg((3 << 11) | 20);  // HW_REG_XCC_ID, bits 3:0
+  const int bin = (int)(xcc % kBatchXcds);
+  int slot = 0;
+  if (lane == 0) {
+    slot = (int)__hip_atomic_fetch_add(sync + kSyncCount + bin, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_or(sync + kSyncMask + bin, 1u << (xcc & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  slot = __shfl(slot, 0);
+  __threadfence();
+  grid.sync();
+  __threadfence();
+  const int nw = (int)sync_load(sync + kSyncCount + bin);
+  const unsigned seen = sync_load(sync + kSyncMask + bin);
+  unsigned flags = 0, imax = 0, isum = 0;
+  // two XCDs in one bin would split a problem over two L2s: refuse to run
+  bool live = (seen & (seen - 1u)) == 0u;
+  if (!live) flags |= RLBM_H_SYNC;
+  // a bin that holds tiles but got no wave would leave its problems unstepped
+  if (wave == 0)
+    for (int x = 0; x < kBatchXcds; ++x)
+      if (a.xoff[x + 1] > a.xoff[x] && sync_load(sync + kSyncCount + x) == 0u) flags |= RLBM_H_SYNC;
+  const int* mine = a.xtiles + a.xoff[bin];
+  const int nmine = a.xoff[bin + 1] - a.xoff[bin];
   const float* src = (const float*)a.src;
   float* dst = (float*)a.dst;
   int shift = a.shift;
-  unsigned flags = 0, imax = 0, isum = 0;
-  for (int t = 0; t < a.nsteps; ++t) {
+  for (int t = 0; t < a.nsteps && live; ++t) {
     const bool sampling = a.samples != nullptr && (t % a.sample_every) == 0;
-    for (int tile = wave; tile < a.ntiles; tile += nwaves) {
+    for (int k = slot; k < nmine && live; k += nw) {
+      const int tile = mine[k];
       const RlbmBatchTile tl = a.tiles[tile];
+      // the neighbours' step t - 1 stores sit in this XCD's L2; drop this
+      // CU's L1 copies before pulling across the tile's edges
+      if (t > 0 && !wait_neighbours(sync, tl.left, tl.right, (unsigned)t)) {
+        live = false;
+        flags |= RLBM_H_SYNC;
+        if (lane == 0) __hip_atomic_store(sync + kSyncAbort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      asm volatile("buffer_inv sc0" ::: "memory");
       const int prob = __builtin_amdgcn_readfirstlane(tl.prob);
       const RlbmBatchProblem pr = a.probs[prob];
       const TabPtr tb = as_tab(a.tables[pr.table]);
@@ -1926,13 +1996,12 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(RlbmBatchArgs a) {
         imax = max(imax, it);
         isum += it;
       }
+      // this wave's stores have reached the XCD's L2 before the tile is
+      // marked done (the L1 writes through)
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      if (lane == 0)
+        __hip_atomic_store(sync + kSyncDone + tile, (unsigned)(t + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    // every site of this step is written before any wave reads it in the
-    // next step: device-scope fences around the grid barrier release this
-    // step's stores and keep another XCD's L2 from serving stale lines
-    __threadfence();
-    grid.sync();
-    __threadfence();
     const float* tmp = src;
     src = dst;
     dst = (float*)tmp;
@@ -1940,6 +2009,11 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(RlbmBatchArgs a) {
   }
   // per-wave statistics into the wave's own slot
   wave_stats(a.slots, wave, flags, imax, isum);
+}
+
+__global__ void __launch_bounds__(256) k_fill_u32(unsigned* __restrict__ p, long long n, unsigned v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
 // f = f^eq(n, T, u) of every problem (fields concatenated over the problems)
@@ -2002,6 +2076,9 @@ struct rlbm_batch {
   RlbmSlot* d_slots = nullptr;      // one per wave of the cooperative grid
   RlbmBatchTile* d_tiles = nullptr;  // 64-site tiles of every problem
   int ntiles = 0;
+  int* d_xtiles = nullptr;           // tile indices grouped by XCD bin
+  int xoff[kBatchXcds + 1] = {};
+  unsigned* d_sync = nullptr;        // per-launch hand-over state (kSyncDone + ntiles words)
   int workgroups = 0;                // cooperative grid (kBatchBlock threads each)
   int resident_limit = 0;            // workgroups the device holds at once for k_batch
   double landau_tol = 1e-10;
@@ -2062,11 +2139,36 @@ extern "C" int rlbm_batch_create(rlbm_batch** out, int nstencils, rlbm_ctx* cons
   }
   b->total_sites = sites;
   b->total_elems = elems;
-  // 64-site tiles of every problem, dealt round-robin to the grid's waves
+  // 64-site tiles of every problem; whole problems are dealt to the XCD bins
+  // (largest first, each to the bin with the fewest tiles so far)
   std::vector<RlbmBatchTile> tiles;
-  for (int p = 0; p < nprob; ++p)
-    for (int x0 = 0; x0 < b->h_probs[p].L; x0 += kWave) tiles.push_back(RlbmBatchTile{p, x0});
+  std::vector<int> first(nprob), count(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    first[p] = (int)tiles.size();
+    for (int x0 = 0; x0 < b->h_probs[p].L; x0 += kWave) {
+      const int i = (int)tiles.size();
+      const bool last = x0 + kWave >= b->h_probs[p].L;
+      tiles.push_back(RlbmBatchTile{p, x0, x0 == 0 ? -1 : i - 1, last ? -1 : i + 1});
+    }
+    count[p] = (int)tiles.size() - first[p];
+  }
   b->ntiles = (int)tiles.size();
+  std::vector<int> order(nprob);
+  for (int p = 0; p < nprob; ++p) order[p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return count[u] > count[v]; });
+  std::vector<std::vector<int>> bins(kBatchXcds);
+  std::vector<long long> load(kBatchXcds, 0);
+  for (int p : order) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    for (int i = 0; i < count[p]; ++i) bins[x].push_back(first[p] + i);
+    load[x] += count[p];
+  }
+  std::vector<int> xtiles;
+  for (int x = 0; x < kBatchXcds; ++x) {
+    b->xoff[x] = (int)xtiles.size();
+    xtiles.insert(xtiles.end(), bins[x].begin(), bins[x].end());
+  }
+  b->xoff[kBatchXcds] = (int)xtiles.size();
   // the cooperative grid: one wave per tile, no more workgroups than the
   // device holds at once (a cooperative launch needs them all resident)
   int dev = 0, cus = 0, per_cu = 0;
@@ -2077,7 +2179,11 @@ extern "C" int rlbm_batch_create(rlbm_batch** out, int nstencils, rlbm_ctx* cons
     return bfail("rlbm_batch_create: occupancy query failed");
   }
   b->resident_limit = per_cu * cus;
-  const int want = (b->ntiles + kBatchBlock / kWave - 1) / (kBatchBlock / kWave);
+  // waves are spread evenly over the XCDs, so size the grid for the fullest
+  // bin: one wave per tile there
+  long long fullest = 0;
+  for (int x = 0; x < kBatchXcds; ++x) fullest = std::max<long long>(fullest, b->xoff[x + 1] - b->xoff[x]);
+  const int want = (int)((fullest * kBatchXcds + kBatchBlock / kWave - 1) / (kBatchBlock / kWave));
   b->workgroups = std::max(1, std::min(want, b->resident_limit));
   const int nwaves = b->workgroups * (kBatchBlock / kWave);
   std::vector<const RlbmTable*> tabs(nstencils);
@@ -2085,13 +2191,16 @@ extern "C" int rlbm_batch_create(rlbm_batch** out, int nstencils, rlbm_ctx* cons
   if (hipMalloc((void**)&b->d_probs, sizeof(RlbmBatchProblem) * nprob) != hipSuccess ||
       hipMalloc((void**)&b->d_tables, sizeof(RlbmTable*) * nstencils) != hipSuccess ||
       hipMalloc((void**)&b->d_slots, sizeof(RlbmSlot) * nwaves) != hipSuccess ||
-      hipMalloc((void**)&b->d_tiles, sizeof(RlbmBatchTile) * b->ntiles) != hipSuccess) {
+      hipMalloc((void**)&b->d_tiles, sizeof(RlbmBatchTile) * b->ntiles) != hipSuccess ||
+      hipMalloc((void**)&b->d_xtiles, sizeof(int) * b->ntiles) != hipSuccess ||
+      hipMalloc((void**)&b->d_sync, sizeof(unsigned) * (kSyncDone + b->ntiles)) != hipSuccess) {
     rlbm_batch_destroy(b);
     return bfail("rlbm_batch_create: device allocation failed");
   }
   BHIP(hipMemcpy(b->d_probs, b->h_probs.data(), sizeof(RlbmBatchProblem) * nprob, hipMemcpyHostToDevice));
   BHIP(hipMemcpy(b->d_tables, tabs.data(), sizeof(RlbmTable*) * nstencils, hipMemcpyHostToDevice));
   BHIP(hipMemcpy(b->d_tiles, tiles.data(), sizeof(RlbmBatchTile) * b->ntiles, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(b->d_xtiles, xtiles.data(), sizeof(int) * b->ntiles, hipMemcpyHostToDevice));
   BHIP(hipMemset(b->d_slots, 0, sizeof(RlbmSlot) * nwaves));
   *out = b;
   return RLBM_OK;
@@ -2112,6 +2221,8 @@ extern "C" int rlbm_batch_destroy(rlbm_batch* b) {
   if (b->d_tables) (void)hipFree((void*)b->d_tables);
   if (b->d_slots) (void)hipFree(b->d_slots);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
+  if (b->d_xtiles) (void)hipFree(b->d_xtiles);
+  if (b->d_sync) (void)hipFree(b->d_sync);
   delete b;
   return RLBM_OK;
 }
@@ -2159,6 +2270,13 @@ extern "C" int rlbm_batch_step_persistent(rlbm_batch* b, int nsteps, int sample_
   a.slots = b->d_slots;
   a.tiles = b->d_tiles;
   a.ntiles = b->ntiles;
+  a.sync = b->d_sync;
+  a.xtiles = b->d_xtiles;
+  for (int x = 0; x <= kBatchXcds; ++x) a.xoff[x] = b->xoff[x];
+  const long long nsync = kSyncDone + b->ntiles;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)std::min<long long>((nsync + 255) / 256, 1024)), dim3(256), 0,
+                     (hipStream_t)stream, b->d_sync, nsync, 0u);
+  BHIP(hipGetLastError());
   void* kargs[] = {&a};
   BHIP(hipLaunchCooperativeKernel((const void*)k_batch, dim3(b->workgroups), dim3(kBatchBlock), kargs, 0,
                                   (hipStream_t)stream));

@@ -24,7 +24,7 @@ BC = {"periodic": 0, "outflow": 1}
 TAU_CONST, TAU_ETA_OVER_S = 0, 1
 ELEM_DTYPE = {"fp64": "float64", "fp32": "float32", "fp16": "float16"}
 
-H_NAN, H_LANDAU, H_SUPERLUMINAL, H_RANGE, H_EOS = 1, 2, 4, 8, 16
+H_NAN, H_LANDAU, H_SUPERLUMINAL, H_RANGE, H_EOS, H_SYNC = 1, 2, 4, 8, 16, 32
 
 EXPORTS = ["rlbm_init_stencil", "rlbm_solve_stencil", "rlbm_class_table", "rlbm_destroy",
            "rlbm_population_bytes", "rlbm_init_fields", "rlbm_step", "rlbm_moments",

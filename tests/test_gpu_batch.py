@@ -64,13 +64,15 @@ def test_batch_matches_oracle_full_horizon():
 
 def test_batch_64_problems_full_horizon_healthy():
     """The full 64-problem, 500-step workload in one launch over the whole
-    chip: no health flag of any kind, finite fields, and a grid of one wave
-    per 64-site tile within the device's resident limit."""
+    chip: no health flag of any kind (the neighbour hand-over included),
+    finite fields, and a grid of at least one wave per 64-site tile within
+    the device's resident limit."""
     problems, fields = workloads.batched_riemann(nprob=64, seed=0)
     b = build_batch(problems, fields)
     occ = b.occupancy()
     assert occ["tiles"] == sum((p["nx"] + 63) // 64 for p in problems)
-    assert occ["workgroups"] == min((occ["tiles"] + 3) // 4, occ["resident_limit"])
+    # at least one wave per tile (the grid is sized for the fullest XCD bin)
+    assert min((occ["tiles"] + 3) // 4, occ["resident_limit"]) <= occ["workgroups"] <= occ["resident_limit"]
     b.step(500)
     h = b.health()
     out = b.moments()
