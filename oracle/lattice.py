@@ -35,6 +35,7 @@ from . import quadrature as quad
 from .projections import projections
 from .eos import temperature
 from .landau import landau_frame
+from . import third_order
 
 HBARC_GEV_FM = 0.1973269804
 
@@ -42,10 +43,11 @@ HBARC_GEV_FM = 0.1973269804
 class PopulationSet:
     """disp [Q, 2] in-plane displacement, p [Q, d] momenta (d = 4 full,
     3 for 2D classes (p0, px, py), 2 for 1D classes (p0, px)), M [Q, 14]
-    = sum over members of w_i J^(k)(p_i); disp3 [Q, 3] the full 3D
-    displacement (full stencils only)."""
+    = sum over members of w_i J^(k)(p_i) (M [Q, 30] at third order);
+    disp3 [Q, 3] the full 3D displacement (full stencils only)."""
 
-    def __init__(self, disp, p, M, mbar, v0, coeffs, weights, group_index, disp3=None):
+    def __init__(self, disp, p, M, mbar, v0, coeffs, weights, group_index, disp3=None, order=2):
+        self.order = int(order)
         self.disp3 = None if disp3 is None else np.asarray(disp3, dtype=np.int64)
         self.disp = np.asarray(disp, dtype=np.int64)
         self.p = np.asarray(p, dtype=np.float64)
@@ -65,11 +67,15 @@ class PopulationSet:
         return self.p.shape[1]
 
 
-def build_stencil(bases, mbar, v0, mode="full", dim=2, weights=None, dps=50):
+def build_stencil(bases, mbar, v0, mode="full", dim=2, weights=None, dps=50, order=2):
     """Populations of a stencil.  ``weights``: per-group weights (floats);
-    solved from the orthonormality conditions when None."""
+    solved from the orthonormality conditions of the given order (2: the 14
+    polynomials of Appendix A; 3: the 30 polynomials of ``third_order``)
+    when None."""
+    if order not in (2, 3):
+        raise ValueError("order must be 2 or 3")
     if weights is None:
-        w, _ = quad.weights(bases, mbar, v0, dps)
+        w, _ = (quad.weights if order == 2 else third_order.weights)(bases, mbar, v0, dps)
         weights = [float(x) for x in w]
     pops = quad.abscissae(bases, mbar, v0, dps)
     vec, mom, wt, gid = [], [], [], []
@@ -84,10 +90,13 @@ def build_stencil(bases, mbar, v0, mode="full", dim=2, weights=None, dps=50):
     wt = np.array(wt, dtype=np.float64)
     gid = np.array(gid, dtype=np.int64)
     coeffs = coefficients(mbar)
-    J = np.array(evaluate_printed(mom, mbar))            # [14, Q3]
-    Mfull = (wt[None, :] * J).T                          # [Q3, 14]
+    if order == 2:
+        J = np.array(evaluate_printed(mom, mbar))        # [14, Q3]
+    else:
+        J = third_order.basis(mbar).evaluate(mom)        # [30, Q3]
+    Mfull = (wt[None, :] * J).T                          # [Q3, 14 or 30]
     if mode == "full":
-        return PopulationSet(vec[:, :2], mom, Mfull, mbar, v0, coeffs, weights, gid, disp3=vec)
+        return PopulationSet(vec[:, :2], mom, Mfull, mbar, v0, coeffs, weights, gid, disp3=vec, order=order)
     keyc = 2 if dim == 2 else 1
     keys = {}
     for i in range(len(vec)):
@@ -101,7 +110,7 @@ def build_stencil(bases, mbar, v0, mode="full", dim=2, weights=None, dps=50):
         p.append(mom[i0, :1 + keyc])
         M.append(Mfull[members].sum(axis=0))
         gi.append(key[0])
-    return PopulationSet(disp, p, M, mbar, v0, coeffs, weights, gi)
+    return PopulationSet(disp, p, M, mbar, v0, coeffs, weights, gi, order=order)
 
 
 # ---------------------------------------------------------------- per site
@@ -131,7 +140,10 @@ def four_velocity(ux, uy):
 
 def equilibrium(ps, n, T, U4):
     """f_i^eq = n sum_k b^(k)(U, T) M_{ik}; U4: [S, 4] contravariant."""
-    b = projections(U4, T, ps.mbar, ps.coeffs)          # [14, S]
+    if ps.order == 3:
+        b = third_order.projections(U4, T, ps.mbar)     # [30, S]
+    else:
+        b = projections(U4, T, ps.mbar, ps.coeffs)      # [14, S]
     return np.asarray(n)[None, :] * (ps.M @ b)
 
 
