@@ -268,6 +268,50 @@ def time_3d(shape=(128, 256, 256), steps=200):
     return out
 
 
+def time_third_order(steps=100):
+    """Third-order model (float64) with the paper's 161-population stencil
+    (Fig. 2b) at mbar = 7.5: a 2D Taylor-Green vortex on 1024^2 (95 merged
+    classes) and a 3D one on 128 x 128 x 64 (all 161 populations).  The step
+    reads every population twice (moments, then collision; the second read
+    mostly hits the caches), so the HBM fraction uses 2 Q 8 bytes per site;
+    the float64 work is ~(14 + 30) Q + 400 multiply-adds per site."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_1703_04605_amd import rlbm
+    from tests.helpers import to_dev
+    st = workloads.THIRD_ORDER
+    out = {"stencil": "G1 G2 G3 G4 G5 G8 G9 G10 G12 G13 G15 (161 populations)", "zeta": st["zeta"]}
+    cases = (("tg2d_1024", 2, to_dev([a[None] for a in workloads.taylor_green(1024, 1024, seed=0)]
+                                     + [np.zeros((1, 1024, 1024))])),
+             ("tg3d_128x128x64", 3, to_dev(workloads.taylor_green_3d(128, 128, 64, seed=0))))
+    for name, dim, f in cases:
+        s = rlbm.Solver3D(st["bases"], st["zeta"], 0.0, order=3, dim=dim)
+        s.init_fields(*f, tau=1.0)
+        s.step(5)
+        s.health(reset=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        h = s.health()
+        q = s.info["q"]
+        sites = f[0].numel()
+        gbs = 2 * q * 8 * sites / (ms * 1e-3) / 1e9
+        fma = (14 + 30) * q + 400
+        out[name] = {"mlups": sites / (ms * 1e-3) / 1e6, "ms_per_step": ms, "classes": q, "v0": s.info["v0"],
+                     "hbm_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                     "fp64_tflops": 2 * fma * sites / (ms * 1e-3) / 1e12,
+                     "fp64_frac": 2 * fma * sites / (ms * 1e-3) / 1e12 / 78.6,
+                     "landau_iter_mean": h["iter_sum"] / (sites * steps), "health_flags": h["flags"]}
+        del s, f
+        torch.cuda.empty_cache()
+    return out
+
+
 def copy_bandwidth(nbytes=4 << 30, reps=10):
     """The achievable HBM rate: the library's streaming copy of nbytes (bytes
     read plus written per second), best grid of a few; torch's copy beside it."""
@@ -347,7 +391,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--only", default=None,
                     help="run a single path of the headline workload (fp32_guess_fixed_point, fp32_fixed_point, "
-                         "fp32, fp64, ...) and print its record, e.g. for a profiler")
+                         "fp32, fp64, ...) or one of third_order, batched, taylor_green_3d (--steps timed "
+                         "steps) and print its record, e.g. for a profiler")
     ap.add_argument("--no-compare", action="store_true", help="headline only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp16-4096", action="store_true", help="skip the 4096^2 float16 flows")
@@ -366,6 +411,12 @@ def main():
     import torch
     import workloads
     from tests.helpers import to_dev
+
+    extra = {"third_order": lambda: time_third_order(args.steps), "batched": lambda: time_batched(args.steps),
+             "taylor_green_3d": lambda: time_3d(steps=args.steps)}
+    if args.only in extra:
+        print(json.dumps({"path": args.only, **extra[args.only]()}))
+        return
 
     if args.calibration_copy:
         from paper_1703_04605_amd import rlbm
@@ -447,6 +498,7 @@ def main():
             del khb
             paths["sheared_flow_4096_fp16"] = {"workload": "Kelvin-Helmholtz 4096^2, 5000 steps", **big}
         paths["taylor_green_3d"] = time_3d()
+        paths["third_order"] = time_third_order()
         paths["batched_riemann"] = time_batched()
         paths["riemann_800"] = time_riemann_800()
     copy = copy_bandwidth()

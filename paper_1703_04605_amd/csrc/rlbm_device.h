@@ -329,6 +329,66 @@ __device__ __forceinline__ double tau_eta_over_s(double tk1, double tk2, double 
   return 0.5 + tk1 * (4.0 - log(tk2 * n / (T * T * T))) / T;
 }
 
+// Third order: the 30 components (kO3Idx order) of the Maxwell-Juttner
+// moment tensors int f^eq p^a .. p^c d^3p/p^0 of rank 0..3, density n
+// included, U contravariant with U^0 = gamma.  With h = eps + P:
+//   rank 0: (eps - 3P)/m^2          (n K_1/(m K_2), by the EOS)
+//   rank 1: n U^a
+//   rank 2: h U^a U^b - P eta^ab
+//   rank 3: (n m^2 + 6 T h) U^a U^b U^c - T h (eta^ab U^c + eta^ac U^b + eta^bc U^a)
+// The rank-3 scalars follow from the mass shell (the trace over one index
+// pair is m^2 n U^c) and from the rest-frame <p0^2> of the distribution.
+__device__ __forceinline__ constexpr double eta_ab(int a, int b) { return a != b ? 0.0 : (a == 0 ? 1.0 : -1.0); }
+
+__device__ __forceinline__ void mj_moments_o3(double n, double eps, double P, double T, double inv_zeta,
+                                              double zeta, const double U[4], double M[RLBM_NO3]) {
+  const double h = eps + P;
+  const double a3 = fma(6.0 * T, h, n * zeta * zeta), b3 = -T * h;
+#pragma unroll
+  for (int i = 0; i < RLBM_NO3; ++i) {
+    const int a = kO3Idx[i][0], b = kO3Idx[i][1], c = kO3Idx[i][2];
+    double v;
+    if (a < 0)
+      v = (eps - 3.0 * P) * inv_zeta * inv_zeta;
+    else if (b < 0)
+      v = n * U[a];
+    else if (c < 0)
+      v = h * U[a] * U[b] - P * eta_ab(a, b);
+    else
+      v = a3 * U[a] * U[b] * U[c] + b3 * (eta_ab(a, b) * U[c] + eta_ab(a, c) * U[b] + eta_ab(b, c) * U[a]);
+    M[i] = v;
+  }
+}
+
+// a_m = int f^eq q_m d^3p/p^0 for the centred, scaled monomials
+// q_m = ((p0 - c)/s0)^k0 (p/sp)^(spatial part of m): the binomial expansion
+// of (p0 - c)^k0 over the raw moments M (exponents and indices resolve at
+// compile time).
+__device__ __forceinline__ void centred_o3(const double M[RLBM_NO3], double c, double is0, double isp,
+                                           double aq[RLBM_NO3]) {
+#pragma unroll
+  for (int m = 0; m < RLBM_NO3; ++m) {
+    const int k0 = o3_exp(m, 0), ks = o3_exp(m, 1) + o3_exp(m, 2) + o3_exp(m, 3);
+    const double m0 = M[kO3Raw.r[m][0]];
+    double v;
+    if (k0 == 0) {
+      v = m0;
+    } else if (k0 == 1) {
+      v = fma(-c, m0, M[kO3Raw.r[m][1]]);
+    } else if (k0 == 2) {
+      v = fma(c * c, m0, fma(-2.0 * c, M[kO3Raw.r[m][1]], M[kO3Raw.r[m][2]]));
+    } else {
+      v = fma(-c * c * c, m0, fma(3.0 * c * c, M[kO3Raw.r[m][1]], fma(-3.0 * c, M[kO3Raw.r[m][2]], M[kO3Raw.r[m][3]])));
+    }
+    double sc = 1.0;
+#pragma unroll
+    for (int e = 0; e < k0; ++e) sc *= is0;
+#pragma unroll
+    for (int e = 0; e < ks; ++e) sc *= isp;
+    aq[m] = v * sc;
+  }
+}
+
 // Hardware dispatches workgroup b to XCD b % 8.  Give each XCD a contiguous
 // range of logical tiles so neighbouring rows share an L2 (bijective for any nb).
 __device__ __forceinline__ int xcd_remap(int b, int nb) {

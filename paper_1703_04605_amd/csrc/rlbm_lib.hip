@@ -881,6 +881,116 @@ k_step3(RlbmStepArgs a) {
   wave_stats(a.slots, t, active ? flags : 0u, active ? (unsigned)iters : 0u, active ? (unsigned)iters : 0u);
 }
 
+// Third-order step (float64 storage; every dimension runs on the 3D
+// layout, merged classes included).  Two passes over the populations: the
+// first pulls them (exact streaming) and sums the 14 moments; the second
+// pulls them again (the same addresses, now in cache), forms each
+// equilibrium from the 30 projections on the centred, scaled monomials and
+// the population's row (eq. mj-projected-distribution at N = 3), relaxes and
+// stores.  No
+// population stays in registers, so any class count fits.
+__global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
+  typedef const __attribute__((address_space(4))) unsigned* OffPtr;
+  const TabPtr tb = as_tab(a.tab);
+  const RlbmLayout& L = a.L;
+  const int lane = (int)threadIdx.x & (kWave - 1);
+  const int t = xcd_remap((int)blockIdx.x, (int)gridDim.x) * (kStepBlock / kWave) +
+                __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  if (t >= a.ntiles) return;  // whole wave
+  const int Q = tb->c.Q;
+  const int row = t / a.tiles_x;  // z * ny + y
+  const int z = row / L.ny, y = row - z * L.ny;
+  const int x0 = (t - row * a.tiles_x) * kWave;
+  const int x = x0 + lane;
+  const bool active = x < L.nx;
+  const int nvalid = min(kWave, L.nx - x0);
+  const long long lo =
+      (long long)(z + L.GZ - L.Sz) * L.zs + (long long)(y + L.GY - L.Sy) * L.rs + L.GX - L.Sx + x0;
+  const __amdgpu_buffer_rsrc_t rs_ld = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)((const char*)a.src + lo * (long long)sizeof(double)), (short)0, kRecAll, kRsrcWord3);
+  const __amdgpu_buffer_rsrc_t rs_st = __builtin_amdgcn_make_buffer_rsrc(
+      (void*)((char*)a.dst + lo * (long long)sizeof(double)), (short)0, kRecAll, kRsrcWord3);
+  const int vld = min(lane, nvalid - 1) * (int)sizeof(double);
+  const int vst = active ? lane * (int)sizeof(double) : kRecOut;
+  const OffPtr pull = (OffPtr)a.offs;
+  const OffPtr own = (OffPtr)a.offs_st;
+
+  double m[RLBM_NB3];
+#pragma unroll
+  for (int k = 0; k < RLBM_NB3; ++k) m[k] = 0.0;
+  for (int j = 0; j < Q; ++j) {
+    const double f = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs_ld, vld, pull[j], 0));
+#pragma unroll
+    for (int k = 0; k < RLBM_NB3; ++k) m[k] = fma(f, tb->rowm3d[j][k], m[k]);
+  }
+
+  // Landau frame, density, EOS
+  unsigned flags = 0;
+  double eps, u[3];
+  const int iters = landau_newton3(m, newton_thresh(a.landau_tol), a.landau_maxit, eps, u, m[4]);
+  if (iters > a.landau_maxit) flags |= RLBM_H_LANDAU;
+  const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  if (!(u2 < 1.0)) flags |= RLBM_H_SUPERLUMINAL;
+  const double gamma = rsqrt_nr(1.0 - u2);
+  const double n = gamma * (m[0] - u[0] * m[1] - u[1] * m[2] - u[2] * m[3]);
+  if (!(n > 0.0) || !(eps > 0.0)) flags |= RLBM_H_RANGE;
+  const double T = eos_temperature_tab(tb, div_nr(eps, n), tb->c.zeta, flags);
+  if (!isfinite(T) || !isfinite(eps) || !isfinite(n)) flags |= RLBM_H_NAN;
+  const double tau = a.tau_mode == RLBM_TAU_CONST ? a.tau : tau_eta_over_s(a.tk1, a.tk2, n, T);
+  const double U[4] = {gamma, gamma * u[0], gamma * u[1], gamma * u[2]};
+  double Mr[RLBM_NO3], M[RLBM_NO3];
+  mj_moments_o3(n, eps, n * T, T, tb->c.inv_zeta, tb->c.zeta, U, Mr);
+  centred_o3(Mr, tb->c.o3_c, tb->c.o3_is0, tb->c.o3_isp, M);
+  const double w0 = a.tau_mode == RLBM_TAU_CONST ? gamma * a.inv_tau : div_nr(gamma, tau);
+  const double v0 = tb->c.v0;
+  const double WX = -w0 * v0 * u[0], WY = -w0 * v0 * u[1], WZ = -w0 * v0 * u[2];
+
+  const unsigned zm = (z < L.Sz || z >= L.nz - L.Sz) ? ghost_mask(z, L.nz, L.Sz, L.bc_z) : 0u;
+  const unsigned ym = (y < L.Sy || y >= L.ny - L.Sy) ? ghost_mask(y, L.ny, L.Sy, L.bc_y) : 0u;
+  const bool xedge = x0 < L.Sx || x0 + kWave > L.nx - L.Sx;
+  const bool ghosts = xedge || ym != 0u || zm != 0u;
+  const unsigned xm = xedge ? ghost_mask(x, L.nx, L.Sx, L.bc_x) : 0u;
+  double* __restrict__ dst = (double*)a.dst;
+  for (int j = 0; j < Q; ++j) {
+    const double f = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs_ld, vld, pull[j], 0));
+    const auto& r = tb->rowo3[j];
+    double feq = M[0] * r[0];
+#pragma unroll
+    for (int k = 1; k < RLBM_NO3; ++k) feq = fma(M[k], r[k], feq);
+    const double om = fma(WZ, r[RLBM_RO3_NZ], fma(WY, r[RLBM_RO3_NY], fma(WX, r[RLBM_RO3_NX], w0)));
+    const double out = fma(-om, f - feq, f);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, out), rs_st, vst, own[j], 0);
+    if (ghosts && active) store_ghosts3(dst + (long long)j * L.cs, L, x, y, z, xm, ym, zm, out);
+  }
+  wave_stats(a.slots, t, active ? flags : 0u, active ? (unsigned)iters : 0u, active ? (unsigned)iters : 0u);
+}
+
+// f_i(x, 0) = f_i^eq(n, T, u) at third order
+__global__ void __launch_bounds__(kBlock) k_init_o3(RlbmInitArgs a, const double* __restrict__ uz) {
+  const TabPtr tb = as_tab(a.tab);
+  const RlbmLayout& L = a.L;
+  const long long site = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (site >= (long long)L.nx * L.ny * L.nz) return;
+  const int x = (int)(site % L.nx);
+  const long long yz = site / L.nx;
+  const int y = (int)(yz % L.ny), z = (int)(yz / L.ny);
+  const double n = a.n[site], T = a.T[site];
+  const double u[3] = {a.ux[site], a.uy[site], uz ? uz[site] : 0.0};
+  const double g = 1.0 / sqrt(1.0 - u[0] * u[0] - u[1] * u[1] - u[2] * u[2]);
+  const double U[4] = {g, g * u[0], g * u[1], g * u[2]};
+  const double eps = n * (3.0 * T + tb->c.zeta * k1k2_ratio(tb->c.zeta / T));
+  double Mr[RLBM_NO3], M[RLBM_NO3];
+  mj_moments_o3(n, eps, n * T, T, tb->c.inv_zeta, tb->c.zeta, U, Mr);
+  centred_o3(Mr, tb->c.o3_c, tb->c.o3_is0, tb->c.o3_isp, M);
+  double* __restrict__ dst = (double*)a.dst;
+  const long long o = (long long)(z + L.GZ) * L.zs + (long long)(y + L.GY) * L.rs + x + L.GX;
+  for (int j = 0; j < tb->c.Q; ++j) {
+    double fe = 0.0;
+    for (int k = 0; k < RLBM_NO3; ++k) fe = fma(M[k], tb->rowo3[j][k], fe);
+    dst[(long long)j * L.cs + o] = fe;
+  }
+}
+
 // 3D fields and raw moments of the current (pre-collision) state
 template <int P>
 __global__ void __launch_bounds__(kBlock) k_moments3(RlbmMomArgs a, double* __restrict__ uz,
@@ -1183,7 +1293,7 @@ extern "C" int rlbm_init_stencil(rlbm_ctx** out, const rlbm_stencil_desc* desc, 
   // a generated fixed-stencil kernel applies when this table is the one it was generated from
   c->fixed_id = -1;
   const uint64_t fp = rlbm_table_fingerprint(c->h_tab);
-  for (int i = 0; i < rlbm_fixed::kNumFixed; ++i)
+  for (int i = 0; i < rlbm_fixed::kNumFixed && c->h_tab->c.order == 2; ++i)
     if (rlbm_fixed::kFixedTables[i].fingerprint == fp && rlbm_fixed::kFixedTables[i].precision == c->h_tab->c.precision)
       c->fixed_id = i;
   hipError_t e = hipGetDevice(&c->device);
@@ -1279,6 +1389,10 @@ extern "C" int rlbm_destroy(rlbm_ctx* c) {
 // interior class row starts on a 32-element boundary; ghost rows of the max
 // |n_y|; the Q class rows of a lattice row are consecutive.
 // 3D lattices stack nz + 2 GZ planes of storage rows (GZ = max |n_z|).
+// Stencils whose lattices run on the 3D layout and entry points (3D
+// stencils, and third-order stencils of every dimension).
+static bool layout3(const RlbmConsts& k) { return k.dim == 3 || k.order == 3; }
+
 static RlbmLayout make_layout(const RlbmConsts& k, int nx, int ny, int bc_x, int bc_y, int nz = 1, int bc_z = 0) {
   RlbmLayout L;
   L.nx = nx;
@@ -1303,13 +1417,14 @@ static RlbmLayout make_layout(const RlbmConsts& k, int nx, int ny, int bc_x, int
 }
 
 extern "C" size_t rlbm_population_bytes(const rlbm_ctx* c, int nx, int ny) {
-  if (!c || nx <= 0 || ny <= 0 || c->h_tab->c.dim == 3) return 0;
+  if (!c || nx <= 0 || ny <= 0 || layout3(c->h_tab->c)) return 0;
   RlbmLayout L = make_layout(c->h_tab->c, nx, ny, 0, 0);
   return (size_t)L.total * elem_size(c->h_tab->c.precision);
 }
 
 extern "C" size_t rlbm_population_bytes3(const rlbm_ctx* c, int nx, int ny, int nz) {
-  if (!c || nx <= 0 || ny <= 0 || nz <= 0 || c->h_tab->c.dim != 3) return 0;
+  if (!c || nx <= 0 || ny <= 0 || nz <= 0 || !layout3(c->h_tab->c)) return 0;
+  if (c->h_tab->c.dim != 3 && (nz != 1 || (c->h_tab->c.dim == 1 && ny != 1))) return 0;
   RlbmLayout L = make_layout(c->h_tab->c, nx, ny, 0, 0, nz, 0);
   return (size_t)L.total * elem_size(c->h_tab->c.precision);
 }
@@ -1331,7 +1446,8 @@ static const char* check_lattice(const RlbmTable& t, const rlbm_lattice_desc* la
   if ((long long)lat->nx * lat->ny * nz > (1LL << 31) - 1) return "lattice too large";
   if (lat->bc_x < 0 || lat->bc_x > 1 || lat->bc_y < 0 || lat->bc_y > 1) return "invalid bc";
   if (k.dim == 3 && (lat->bc_z < 0 || lat->bc_z > 1)) return "invalid bc_z";
-  if (k.dim == 3 && lat->landau_method != RLBM_LANDAU_NEWTON) return "3D lattices solve the Landau frame by Newton";
+  if (layout3(k) && lat->landau_method != RLBM_LANDAU_NEWTON)
+    return "3D and third-order lattices solve the Landau frame by Newton";
   if (lat->tau_mode == RLBM_TAU_CONST) {
     if (!(lat->tau > 0.5)) return "tau must exceed 1/2";
   } else if (lat->tau_mode == RLBM_TAU_ETA_OVER_S) {
@@ -1395,15 +1511,15 @@ static int init_fields_impl(rlbm_ctx* c, const rlbm_lattice_desc* lat, const dou
                             size_t pop_bytes, void* stream, bool use_static, bool three_d) {
   if (!c || !lat) return fail(c, RLBM_EINVAL, "NULL context or lattice");
   const RlbmConsts& k = c->h_tab->c;
-  if ((k.dim == 3) != three_d)
-    return fail(c, RLBM_EINVAL, "%s", three_d ? "rlbm_init_fields3 needs a 3D stencil (dim 3)"
-                                              : "3D stencils take rlbm_init_fields3");
+  if (layout3(k) != three_d)
+    return fail(c, RLBM_EINVAL, "%s", three_d ? "rlbm_init_fields3 needs a 3D or third-order stencil"
+                                              : "3D and third-order stencils take rlbm_init_fields3");
   RlbmLayout L;
   RlbmOffsetsArg offs;
   if (const char* why = check_lattice(*c->h_tab, lat, L, offs.v)) return fail(c, RLBM_EINVAL, "%s", why);
   if (!n || !T || !ux || !uy || (three_d && !uz) || !popA || !popB || popA == popB)
     return fail(c, RLBM_EINVAL, "NULL field or population buffer");
-  const int nz = three_d ? lat->nz : 1;
+  const int nz = k.dim == 3 ? lat->nz : 1;
   const size_t need = three_d ? rlbm_population_bytes3(c, lat->nx, lat->ny, nz)
                               : rlbm_population_bytes(c, lat->nx, lat->ny);
   if (pop_bytes < need) return fail(c, RLBM_EINVAL, "population buffer too small");
@@ -1477,7 +1593,9 @@ static int init_fields_impl(rlbm_ctx* c, const rlbm_lattice_desc* lat, const dou
   ia.tab = c->d_tab;
   long long sites = (long long)lat->nx * lat->ny * nz;
   dim3 grid((unsigned)((sites + kBlock - 1) / kBlock));
-  if (three_d) {
+  if (k.order == 3) {
+    hipLaunchKernelGGL(k_init_o3, grid, dim3(kBlock), 0, s, ia, uz);
+  } else if (three_d) {
     switch (k.precision) {
       case RLBM_FP64: hipLaunchKernelGGL(k_init3<RLBM_FP64>, grid, dim3(kBlock), 0, s, ia, uz); break;
       case RLBM_FP32_DEV: hipLaunchKernelGGL(k_init3<RLBM_FP32_DEV>, grid, dim3(kBlock), 0, s, ia, uz); break;
@@ -1537,8 +1655,9 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
     for (int i = 0; i < 24; ++i) a.mlp_norm[i] = c->guess->h_norm[i];
     for (int i = 0; i < 9; ++i) a.mlp_norm[9 + i] = 1.0f / c->guess->h_norm[9 + i];
   }
-  const bool d3 = c->h_tab->c.dim == 3;
+  const bool d3 = layout3(c->h_tab->c);
   StepFn fn = (!d3 && c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? fixed_step(c->fixed_id, g) : nullptr;
+  if (!fn && c->h_tab->c.order == 3) fn = k_step_o3;
   if (!fn) fn = d3 ? select_step3(c->h_tab->c.precision, c->h_tab->c.Q) : select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
   if (!fn) return fail(c, RLBM_ESTATE, "no step kernel for this stencil");
   a.tiles_x = c->tiles_x;
@@ -1572,7 +1691,7 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
 extern "C" int rlbm_moments3(rlbm_ctx* c, double* n, double* eps, double* T, double* P, double* ux, double* uy,
                              double* uz, double* raw14, void* stream) {
   if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
-  if (c->h_tab->c.dim != 3) return fail(c, RLBM_EINVAL, "rlbm_moments3 needs a 3D stencil");
+  if (!layout3(c->h_tab->c)) return fail(c, RLBM_EINVAL, "rlbm_moments3 needs a 3D or third-order stencil");
   if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_moments3 before rlbm_init_fields3");
   RlbmMomArgs a;
   a.src = c->buf[c->cur];
@@ -1598,7 +1717,7 @@ extern "C" int rlbm_moments3(rlbm_ctx* c, double* n, double* eps, double* T, dou
 extern "C" int rlbm_moments(rlbm_ctx* c, double* n, double* eps, double* T, double* P, double* ux, double* uy,
                             double* raw9, void* stream) {
   if (!c) return fail(nullptr, RLBM_EINVAL, "NULL context");
-  if (c->h_tab->c.dim == 3) return fail(c, RLBM_EINVAL, "3D stencils take rlbm_moments3");
+  if (layout3(c->h_tab->c)) return fail(c, RLBM_EINVAL, "3D and third-order stencils take rlbm_moments3");
   if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_moments before rlbm_init_fields");
   RlbmMomArgs a;
   a.src = c->buf[c->cur];
@@ -1702,7 +1821,7 @@ extern "C" int rlbm_set_warm_start(rlbm_ctx* c, int enable) {
   }
   if (!c->have_fields) return fail(c, RLBM_ESTATE, "rlbm_set_warm_start before rlbm_init_fields");
   if (c->guess) return fail(c, RLBM_EINVAL, "the learned guess and the warm start are exclusive");
-  if (c->h_tab->c.dim == 3) return fail(c, RLBM_EINVAL, "the warm start is available in 1D and 2D");
+  if (layout3(c->h_tab->c)) return fail(c, RLBM_EINVAL, "the warm start is available for second-order 1D and 2D stencils");
   const size_t need = (size_t)3 * c->L.nx * c->L.ny;
   if (c->warm_cap < need) {
     if (c->d_warm) HIPCHECK(c, hipFree(c->d_warm));

@@ -32,6 +32,7 @@ struct rlbm_mlp {
   float* D[3] = {nullptr, nullptr, nullptr};
   unsigned short* frag = nullptr;  // bf16 weight fragments for the in-step inference
   float* biasfrag = nullptr;       // bias fragments (accumulator layout)
+  float* part = nullptr;           // per-chunk partial weight gradients [chunks][64][65]
 };
 
 // Re-rounds the bf16 copies and re-packs the fragments after a weight change.

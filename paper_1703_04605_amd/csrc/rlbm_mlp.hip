@@ -90,20 +90,49 @@ __global__ void k_bwd_act(const float* __restrict__ d, int nout, const float* __
   dprev[t] = s * dsilu(zprev[t]);
 }
 
-// gW[o][i] = sum_b d[b][o] a[b][i], gb[o] = sum_b d[b][o]; one thread per (o, i) and (o, nin)
-__global__ void k_bwd_w(const float* __restrict__ d, int nout, const float* __restrict__ A, int nin, int B,
-                        float* __restrict__ gW, float* __restrict__ gb) {
+// Weight gradients gW[o][i] = sum_b d[b][o] a[b][i], gb[o] = sum_b d[b][o],
+// in two deterministic passes: each workgroup stages a chunk of kChunk batch
+// rows of d and a in LDS and writes the chunk's partial sums for every
+// (o, i) (i = nin: the bias); a second pass adds the chunks in order.
+constexpr int kChunk = 64;
+constexpr int kMaxUnits = 64;
+
+__global__ void __launch_bounds__(kT) k_bwd_w_part(const float* __restrict__ d, int nout, const float* __restrict__ A,
+                                                   int nin, int B, float* __restrict__ part) {
+  __shared__ float ds[kChunk][kMaxUnits];
+  __shared__ float as[kChunk][kMaxUnits + 1];
+  const int b0 = blockIdx.x * kChunk;
+  const int rows = min(kChunk, B - b0);
+  for (int e = threadIdx.x; e < kChunk * kMaxUnits; e += kT) {
+    const int r = e / kMaxUnits, c = e - r * kMaxUnits;
+    ds[r][c] = (r < rows && c < nout) ? d[(long long)(b0 + r) * nout + c] : 0.0f;
+    as[r][c] = (r < rows && c < nin) ? A[(long long)(b0 + r) * nin + c] : 0.0f;
+  }
+  for (int r = threadIdx.x; r < kChunk; r += kT) as[r][kMaxUnits] = r < rows ? 1.0f : 0.0f;
+  __syncthreads();
+  const int nel = nout * (nin + 1);
+  float* out = part + (long long)blockIdx.x * kMaxUnits * (kMaxUnits + 1);
+  for (int t = threadIdx.x; t < nel; t += kT) {
+    const int o = t / (nin + 1), i = t - o * (nin + 1);
+    const int col = i < nin ? i : kMaxUnits;  // the bias column holds ones
+    float s = 0.0f;
+#pragma unroll 16
+    for (int r = 0; r < kChunk; ++r) s = fmaf(ds[r][o], as[r][col], s);
+    out[t] = s;
+  }
+}
+
+__global__ void __launch_bounds__(kT) k_bwd_w_sum(const float* __restrict__ part, int chunks, int nout, int nin,
+                                                  float* __restrict__ gW, float* __restrict__ gb) {
   const int t = blockIdx.x * kT + threadIdx.x;
   if (t >= nout * (nin + 1)) return;
-  const int o = t / (nin + 1), i = t - o * (nin + 1);
   float s = 0.0f;
-  if (i < nin) {
-    for (int b = 0; b < B; ++b) s = fmaf(d[b * nout + o], A[b * nin + i], s);
+  for (int c = 0; c < chunks; ++c) s += part[(long long)c * kMaxUnits * (kMaxUnits + 1) + t];
+  const int o = t / (nin + 1), i = t - o * (nin + 1);
+  if (i < nin)
     gW[o * nin + i] = s;
-  } else {
-    for (int b = 0; b < B; ++b) s += d[b * nout + o];
+  else
     gb[o] = s;
-  }
 }
 
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
@@ -225,7 +254,9 @@ extern "C" int rlbm_mlp_create(rlbm_mlp** out, const float* params, const float*
   if (hipMalloc((void**)&m->frag, sizeof(unsigned short) * 8 * RLBM_MLP_NFRAG * 64) != hipSuccess ||
       hipMalloc((void**)&m->biasfrag, sizeof(float) * 16 * RLBM_MLP_NBFRAG * 64) != hipSuccess ||
       hipMalloc((void**)&m->Z4, sizeof(float) * 3 * (size_t)max_batch) != hipSuccess ||
-      hipMalloc((void**)&m->D[0], sizeof(float) * 3 * act) != hipSuccess) {
+      hipMalloc((void**)&m->D[0], sizeof(float) * 3 * act) != hipSuccess ||
+      hipMalloc((void**)&m->part, sizeof(float) * (size_t)((max_batch + kChunk - 1) / kChunk) * kMaxUnits *
+                                      (kMaxUnits + 1)) != hipSuccess) {
     rlbm_mlp_destroy(m);
     return mfail("rlbm_mlp_create: device allocation failed");
   }
@@ -257,6 +288,7 @@ extern "C" int rlbm_mlp_destroy(rlbm_mlp* m) {
   if (m->biasfrag) (void)hipFree(m->biasfrag);
   if (m->Z4) (void)hipFree(m->Z4);
   if (m->D[0]) (void)hipFree(m->D[0]);
+  if (m->part) (void)hipFree(m->part);
   delete m;
   return RLBM_OK;
 }
@@ -287,8 +319,10 @@ extern "C" int rlbm_mlp_train_step(rlbm_mlp* m, const float* raw9, const float* 
   for (int L = 3; L >= 0; --L) {
     const int nin = RLBM_MLP_IN[L], nout = RLBM_MLP_OUT[L];
     const float* Aprev = L > 0 ? m->A[L - 1] : m->X;
-    hipLaunchKernelGGL(k_bwd_w, grid_of((long long)nout * (nin + 1)), dim3(kT), 0, s, d, nout, Aprev, nin, B,
-                       m->grad + RLBM_MLP_WOFF[L], m->grad + RLBM_MLP_BOFF[L]);
+    const int chunks = (B + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_bwd_w_part, dim3(chunks), dim3(kT), 0, s, d, nout, Aprev, nin, B, m->part);
+    hipLaunchKernelGGL(k_bwd_w_sum, grid_of((long long)nout * (nin + 1)), dim3(kT), 0, s, m->part, chunks, nout,
+                       nin, m->grad + RLBM_MLP_WOFF[L], m->grad + RLBM_MLP_BOFF[L]);
     if (L > 0) {
       hipLaunchKernelGGL(k_bwd_act, grid_of((long long)B * nin), dim3(kT), 0, s, d, nout, m->bf + RLBM_MLP_WOFF[L],
                          nin, m->Z[L - 1], B, m->D[L - 1]);

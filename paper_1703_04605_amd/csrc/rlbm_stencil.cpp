@@ -269,16 +269,519 @@ void set_err(char* err, size_t len, const char* msg) {
   if (err && len) snprintf(err, len, "%s", msg);
 }
 
+// ---- third order (Sec. III.A, III.D) ----
+
+// R[j][s] = <p0^j |p|^s> under omega (s even, angular part excluded), j, s <= 6:
+// m^(j+s) S(j, s) / S(0, 0) with S(j, s) = int exp(-m (cosh t - 1))
+// cosh^j t sinh^(2+s) t dt (trapezoid rule; the integrand is even in t).
+void omega_radial_moments(ld m, ld R[7][7]) {
+  const ld h = std::min(1.0L / 8.0L, 0.5L / sqrtl(m));
+  ld S[7][7] = {};
+  for (int k = 0; k < 400000; ++k) {
+    const ld t = k * h, c = coshl(t), sh = sinhl(t);
+    const ld e = expl(-m * (c - 1.0L)) * sh * sh * (k == 0 ? 0.5L : 1.0L);
+    ld cj = 1.0L;
+    for (int j = 0; j < 7; ++j) {
+      ld ss = 1.0L;
+      for (int q = 0; q < 7; ++q) {
+        S[j][q] += e * cj * ss;
+        ss *= sh;
+      }
+      cj *= c;
+    }
+    if (m * (c - 1.0L) > 90.0L + 13.0L * t) break;
+  }
+  for (int j = 0; j < 7; ++j)
+    for (int q = 0; q < 7; ++q) R[j][q] = powl(m, (ld)(j + q)) * S[j][q] / S[0][0];
+}
+
+// <n_x^a n_y^b n_z^c> over the unit sphere: (a-1)!!(b-1)!!(c-1)!!/(a+b+c+1)!!
+// for even exponents, 0 otherwise
+ld sphere_avg(int a, int b, int c) {
+  if ((a | b | c) & 1) return 0.0L;
+  auto dfact = [](int n) {
+    ld r = 1.0L;
+    for (int k = n; k > 1; k -= 2) r *= k;
+    return r;
+  };
+  return dfact(a - 1) * dfact(b - 1) * dfact(c - 1) / dfact(a + b + c + 1);
+}
+
+// exponents (k0, kx, ky, kz) of monomial m of the third-order list
+void o3_exponents(int mono, int e[4]) {
+  e[0] = e[1] = e[2] = e[3] = 0;
+  for (int r = 0; r < 3; ++r)
+    if (kO3Idx[mono][r] >= 0) ++e[kO3Idx[mono][r]];
+}
+
+struct Stencil3 {
+  ld m;
+  int ng;
+  std::vector<std::vector<std::array<int, 3>>> orbit;
+  std::vector<int> n2;
+  ld R[7][7];
+  ld vmax;
+  ld rhs[11];
+  ld c = 0, s = 1, sp = 1;  // centre and spread of p0, rms of p_x
+
+  Stencil3(ld mbar, int n_groups, const int* gb) : m(mbar), ng(n_groups) {
+    int maxn2 = 0;
+    for (int g = 0; g < ng; ++g) {
+      const int b[3] = {gb[3 * g], gb[3 * g + 1], gb[3 * g + 2]};
+      orbit.push_back(fs_orbit(b));
+      n2.push_back(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
+      maxn2 = std::max(maxn2, n2.back());
+    }
+    vmax = maxn2 > 0 ? 1.0L / sqrtl((ld)maxn2) : 1.0L;
+    omega_radial_moments(m, R);
+    // The conditions are written in the centred, scaled energy
+    // t = (p0 - c)/s and momentum p/sp (c = <p0>, s its spread, sp^2 = <p_x^2>):
+    // exact integrals of t^j (j <= 6), t^j (p_x/sp)^4 (j <= 2) and
+    // (p_x p_y p_z / sp^3)^2.  They are combinations of the conditions on
+    // p0^j, p0^j p_x^4 and p_x^2 p_y^2 p_z^2 (same solution), far better
+    // conditioned than raw powers of p0 at large mbar.
+    c = R[1][0];
+    s = sqrtl(R[2][0] - c * c);
+    sp = sqrtl(R[0][2] / 3.0L);
+    auto tmom = [this](int j, int k) {  // <t^j |p|^k>
+      ld sum = 0, bin = 1;
+      for (int i = 0; i <= j; ++i) {
+        sum += bin * powl(-c, (ld)(j - i)) * R[i][k];
+        bin = bin * (j - i) / (i + 1);
+      }
+      return sum / powl(s, (ld)j);
+    };
+    for (int j = 0; j < 7; ++j) rhs[j] = tmom(j, 0);
+    for (int j = 0; j < 3; ++j) rhs[7 + j] = tmom(j, 4) * sphere_avg(4, 0, 0) / powl(sp, 4.0L);
+    rhs[10] = R[0][6] * sphere_avg(2, 2, 2) / powl(sp, 6.0L);
+  }
+
+  // the eleven conditions as a square system in the per-population weights
+  bool weights(ld v0, std::vector<ld>& w) const {
+    if (ng != 11) return false;
+    std::vector<ld> a(121, 0.0L), b(rhs, rhs + 11);
+    for (int g = 0; g < 11; ++g) {
+      const ld gam = 1.0L / sqrtl(1.0L - v0 * v0 * n2[g]);
+      const ld t = (m * gam - c) / s, pm = m * gam * v0 / sp;
+      ld pw = 1.0L;
+      for (int j = 0; j < 7; ++j) {
+        a[j * 11 + g] = (ld)orbit[g].size() * pw;
+        pw *= t;
+      }
+      ld x4 = 0, x2y2z2 = 0;
+      for (auto& v : orbit[g]) {
+        x4 += (ld)v[0] * v[0] * v[0] * v[0];
+        x2y2z2 += (ld)v[0] * v[0] * v[1] * v[1] * v[2] * v[2];
+      }
+      const ld pm4 = pm * pm * pm * pm;
+      for (int j = 0; j < 3; ++j) a[(7 + j) * 11 + g] = x4 * pm4 * powl(t, (ld)j);
+      a[10 * 11 + g] = x2y2z2 * pm4 * pm * pm;
+    }
+    return solve_dense(11, a, b, w);
+  }
+
+  ld min_weight(ld v0) const {
+    std::vector<ld> w;
+    if (!weights(v0, w)) return -1e300L;
+    return *std::min_element(w.begin(), w.end());
+  }
+};
+
+// Cholesky factor (lower) of a symmetric positive definite n x n matrix
+bool cholesky(int n, const std::vector<ld>& a, std::vector<ld>& L) {
+  L.assign(n * n, 0.0L);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      ld s = a[i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+      if (i == j) {
+        if (!(s > 0)) return false;
+        L[i * n + i] = sqrtl(s);
+      } else {
+        L[i * n + j] = s / L[j * n + j];
+      }
+    }
+  return true;
+}
+
 }  // namespace
+
+// The interval of v0 in the description's search range on which every
+// weight is positive: grid search for the v0 that maximises the smallest
+// weight (zooming in until it is positive), edges bracketed by doubling steps
+// and bisected, then a check that the interval is one connected run.
+template <class MinW>
+int positive_window(const MinW& minw, ld vmax, const rlbm_stencil_desc* d, ld& wlo, ld& whi, char* err,
+                    size_t errlen) {
+  // search the interval of all-positive weights: grid, zoom on max min_k w_k, bisect edges
+  ld lo = d->v0_lo > 0 ? (ld)d->v0_lo : 1e-6L;
+  ld hi = d->v0_hi > 0 ? std::min((ld)d->v0_hi, vmax * (1 - 1e-12L)) : vmax * (1 - 1e-12L);
+  if (!(hi > lo)) {
+    set_err(err, errlen, "empty v0 search interval");
+    return RLBM_EINVAL;
+  }
+  const int G = 400;
+  ld a = lo, b = hi, best = lo, bestv = -1e300L;
+  for (int zoom = 0; zoom < 14 && bestv <= 0; ++zoom) {
+    ld step = (b - a) / G;
+    for (int i = 0; i <= G; ++i) {
+      ld v = a + step * i;
+      ld mw = minw(v);
+      if (mw > bestv) {
+        bestv = mw;
+        best = v;
+      }
+    }
+    a = std::max(best - 2 * step, lo);
+    b = std::min(best + 2 * step, hi);
+  }
+  if (!(bestv > 0)) {
+    set_err(err, errlen, "no v0 with all weights positive in the search interval");
+    return RLBM_ENOSTENCIL;
+  }
+  // bracket each edge by steps that double from the last grid spacing (after
+  // deep zooming that spacing can be far below the window's width), then bisect
+  const ld step0 = std::max((b - a) / G, (hi - lo) * 1e-15L);
+  ld l_in = best, l_out = lo, r_in = best, r_out = hi;
+  for (ld s = step0; best - s > lo; s *= 2) {
+    if (minw(best - s) > 0) {
+      l_in = best - s;
+    } else {
+      l_out = best - s;
+      break;
+    }
+  }
+  for (ld s = step0; best + s < hi; s *= 2) {
+    if (minw(best + s) > 0) {
+      r_in = best + s;
+    } else {
+      r_out = best + s;
+      break;
+    }
+  }
+  auto bisect = [&minw](ld& in, ld& out) {
+    for (int it = 0; it < 100; ++it) {
+      const ld mid = 0.5L * (in + out);
+      if (minw(mid) > 0) in = mid; else out = mid;
+    }
+  };
+  bisect(l_in, l_out);
+  bisect(r_in, r_out);
+  // A doubled step can jump over a run of negative weights into another
+  // positive run; the window must be the run that holds `best`.  Sample it:
+  // if any interior point is not positive, walk out from `best` at the
+  // finest spacing instead (bounded), and bisect from there.
+  auto connected = [&minw](ld x0, ld x1) {
+    for (int i = 1; i < 64; ++i)
+      if (!(minw(x0 + (x1 - x0) * i / 64) > 0)) return false;
+    return true;
+  };
+  if (!connected(l_in, best) || !connected(best, r_in)) {
+    // (a walk that ends without leaving the run keeps its last point as the
+    // edge: out == in leaves nothing to bisect)
+    l_in = best, r_in = best;
+    l_out = lo, r_out = hi;
+    bool l_found = false, r_found = false;
+    for (int i = 1; i <= 100000 && best - i * step0 > lo; ++i) {
+      if (minw(best - i * step0) > 0) {
+        l_in = best - i * step0;
+      } else {
+        l_out = best - i * step0;
+        l_found = true;
+        break;
+      }
+    }
+    for (int i = 1; i <= 100000 && best + i * step0 < hi; ++i) {
+      if (minw(best + i * step0) > 0) {
+        r_in = best + i * step0;
+      } else {
+        r_out = best + i * step0;
+        r_found = true;
+        break;
+      }
+    }
+    if (l_found) bisect(l_in, l_out);
+    if (r_found) bisect(r_in, r_out);
+  }
+  wlo = l_in;
+  whi = r_in;
+  return RLBM_OK;
+}
 
 // Bessel ratio K1/K2 in long double (host reference state only)
 static ld k1k2_ld(ld z) { return besselk_scaled_ld(1, z) / besselk_scaled_ld(2, z); }
 
+// Third-order quadrature and tables (float64 storage only).  The continuous
+// Gram matrix is taken over a centred, scaled copy q of the 30 monomials,
+// q_m = ((p0 - c)/s0)^k0 (p_x/sp)^kx (p_y/sp)^ky (p_z/sp)^kz with c = <p0>,
+// s0 its spread and sp^2 = <p_x^2> (well conditioned at every mbar);
+// orthonormal polynomials are J = L^-1 q with G_q = L L^T.  The equilibrium
+// f_i = n w_i sum_k a_k J_k(p_i) with a = L^-1 int f^eq q becomes
+// f_i = R_i . a, with a = int f^eq q d^3p/p^0 (formed on the device from
+// the raw moment tensors) and R_i = w_i L^-T J(p_i).
+static int build_table_o3(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTable* tab, char* err,
+                          size_t errlen) {
+  if (d->n_groups != 11 || d->precision != RLBM_FP64) {
+    set_err(err, errlen, "third order needs 11 groups and float64 storage");
+    return RLBM_EINVAL;
+  }
+  Stencil3 st((ld)d->zeta, d->n_groups, d->group_base);
+  for (int g = 0; g < 11; ++g)
+    for (int h = g + 1; h < 11; ++h)
+      if (st.orbit[g] == st.orbit[h]) {
+        set_err(err, errlen, "repeated velocity group");
+        return RLBM_EINVAL;
+      }
+  ld v0 = d->v0;
+  ld wlo = 0, whi = 0;
+  if (d->weights && !(v0 > 0)) {
+    set_err(err, errlen, "given weights need a given v0");
+    return RLBM_EINVAL;
+  }
+  if (!(v0 > 0)) {
+    const int rc = positive_window([&st](ld v) { return st.min_weight(v); }, st.vmax, d, wlo, whi, err, errlen);
+    if (rc) return rc;
+    v0 = 0.5L * (wlo + whi);
+  }
+  if (!(v0 < st.vmax)) {
+    set_err(err, errlen, "v0 too large: a group would move faster than light");
+    return RLBM_EINVAL;
+  }
+  std::vector<ld> w(11);
+  if (d->weights) {
+    for (int g = 0; g < 11; ++g) w[g] = (ld)d->weights[g];
+  } else if (!st.weights(v0, w)) {
+    set_err(err, errlen, "singular quadrature system for this group set");
+    return RLBM_ENOSTENCIL;
+  }
+  for (ld x : w)
+    if (!(x > 0)) {
+      set_err(err, errlen, "quadrature weights not all positive at this v0");
+      return RLBM_ENOSTENCIL;
+    }
+
+  // centred, scaled basis and its continuous Gram matrix
+  const ld m = (ld)d->zeta;
+  const ld c0 = st.R[1][0], s0 = sqrtl(st.R[2][0] - c0 * c0), sp = sqrtl(st.R[0][2] / 3.0L);
+  int ex[RLBM_NO3][4];
+  for (int a = 0; a < RLBM_NO3; ++a) o3_exponents(a, ex[a]);
+  auto binom = [](int n, int k) {
+    ld r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+  };
+  // B[a][r]: coefficient of raw monomial r in q_a
+  std::vector<ld> B(RLBM_NO3 * RLBM_NO3, 0.0L);
+  for (int a = 0; a < RLBM_NO3; ++a)
+    for (int r = 0; r < RLBM_NO3; ++r) {
+      if (ex[r][1] != ex[a][1] || ex[r][2] != ex[a][2] || ex[r][3] != ex[a][3] || ex[r][0] > ex[a][0]) continue;
+      const int K = ex[a][0], k = ex[r][0];
+      B[a * RLBM_NO3 + r] = binom(K, k) * powl(-c0, (ld)(K - k)) /
+                            (powl(s0, (ld)K) * powl(sp, (ld)(ex[a][1] + ex[a][2] + ex[a][3])));
+    }
+  std::vector<ld> G(RLBM_NO3 * RLBM_NO3, 0.0L);
+  for (int a = 0; a < RLBM_NO3; ++a)
+    for (int b = 0; b < RLBM_NO3; ++b) {
+      ld sum = 0;
+      for (int r = 0; r < RLBM_NO3; ++r) {
+        const ld br = B[a * RLBM_NO3 + r];
+        if (br == 0) continue;
+        for (int t = 0; t < RLBM_NO3; ++t) {
+          const ld bt = B[b * RLBM_NO3 + t];
+          if (bt == 0) continue;
+          const int e0 = ex[r][0] + ex[t][0], ex_ = ex[r][1] + ex[t][1], ey = ex[r][2] + ex[t][2],
+                    ez = ex[r][3] + ex[t][3];
+          sum += br * bt * st.R[e0][ex_ + ey + ez] * sphere_avg(ex_, ey, ez);
+        }
+      }
+      G[a * RLBM_NO3 + b] = sum;
+    }
+  std::vector<ld> L;
+  if (!cholesky(RLBM_NO3, G, L)) {
+    set_err(err, errlen, "third-order Gram matrix not positive definite");
+    return RLBM_EINVAL;
+  }
+  auto lower_solve = [&L](const ld* y, ld* x) {  // x = L^-1 y
+    for (int i = 0; i < RLBM_NO3; ++i) {
+      ld s = y[i];
+      for (int k = 0; k < i; ++k) s -= L[i * RLBM_NO3 + k] * x[k];
+      x[i] = s / L[i * RLBM_NO3 + i];
+    }
+  };
+  auto upper_solve = [&L](const ld* y, ld* x) {  // x = L^-T y
+    for (int i = RLBM_NO3 - 1; i >= 0; --i) {
+      ld s = y[i];
+      for (int k = i + 1; k < RLBM_NO3; ++k) s -= L[k * RLBM_NO3 + i] * x[k];
+      x[i] = s / L[i * RLBM_NO3 + i];
+    }
+  };
+
+  // populations and their orthonormal polynomial values
+  struct P3 { int g; int n[3]; ld p[4]; };
+  std::vector<P3> pops;
+  for (int g = 0; g < 11; ++g) {
+    const ld gam = 1.0L / sqrtl(1.0L - v0 * v0 * st.n2[g]);
+    for (auto& v : st.orbit[g])
+      pops.push_back({g, {v[0], v[1], v[2]}, {m * gam, m * gam * v0 * v[0], m * gam * v0 * v[1], m * gam * v0 * v[2]}});
+  }
+  const int np = (int)pops.size();
+  std::vector<std::array<ld, RLBM_NO3>> J(np);
+  for (int i = 0; i < np; ++i) {
+    ld raw[RLBM_NO3], q[RLBM_NO3];
+    for (int r = 0; r < RLBM_NO3; ++r) {
+      ld v = 1;
+      for (int k = 0; k < 3; ++k)
+        if (kO3Idx[r][k] >= 0) v *= pops[i].p[kO3Idx[r][k]];
+      raw[r] = v;
+    }
+    for (int a = 0; a < RLBM_NO3; ++a) {
+      ld sum = 0;
+      for (int r = 0; r < RLBM_NO3; ++r) sum += B[a * RLBM_NO3 + r] * raw[r];
+      q[a] = sum;
+    }
+    lower_solve(q, J[i].data());
+  }
+  // orthonormality of the 30 polynomials under the quadrature (eq. ortho2)
+  ld res = 0;
+  for (int l = 0; l < RLBM_NO3; ++l)
+    for (int k = l; k < RLBM_NO3; ++k) {
+      ld sum = 0;
+      for (int i = 0; i < np; ++i) sum += w[pops[i].g] * J[i][l] * J[i][k];
+      res = std::max(res, fabsl(sum - (l == k ? 1.0L : 0.0L)));
+    }
+  // condition number of the quadrature problem's system matrix (465 x 11)
+  ld cond = INFINITY;
+  {
+    std::vector<ld> AtA(121, 0.0L), row(11);
+    for (int l = 0; l < RLBM_NO3; ++l)
+      for (int k = l; k < RLBM_NO3; ++k) {
+        std::fill(row.begin(), row.end(), 0.0L);
+        for (int i = 0; i < np; ++i) row[pops[i].g] += J[i][l] * J[i][k];
+        for (int g = 0; g < 11; ++g)
+          for (int h = 0; h < 11; ++h) AtA[g * 11 + h] += row[g] * row[h];
+      }
+    std::vector<ld> ev;
+    jacobi_eigenvalues(11, AtA, ev);
+    const ld mx = *std::max_element(ev.begin(), ev.end()), mn = *std::min_element(ev.begin(), ev.end());
+    if (mn > 0) cond = sqrtl(mx / mn);
+  }
+  if (!(res < 1e-10L)) {
+    set_err(err, errlen, "third-order orthonormality conditions not satisfied by this group set");
+    return RLBM_ENOSTENCIL;
+  }
+
+  // classes as at second order
+  std::map<std::tuple<int, int, int, int>, int> key2class;
+  std::vector<std::vector<int>> members;
+  for (int i = 0; i < np; ++i) {
+    auto key = std::make_tuple(pops[i].g, pops[i].n[0], d->dim >= 2 ? pops[i].n[1] : 0,
+                               d->dim == 3 ? pops[i].n[2] : 0);
+    auto it = key2class.find(key);
+    if (it == key2class.end()) {
+      key2class[key] = (int)members.size();
+      members.push_back({i});
+    } else {
+      members[it->second].push_back(i);
+    }
+  }
+  const int Q = (int)members.size();
+  if (Q > RLBM_QMAX) {
+    set_err(err, errlen, "stencil has more population classes than the library supports");
+    return RLBM_EINVAL;
+  }
+  int sx_max = 0, sy_max = 0, sz_max = 0;
+  for (auto& p : pops) {
+    sx_max = std::max(sx_max, abs(p.n[0]));
+    if (d->dim >= 2) sy_max = std::max(sy_max, abs(p.n[1]));
+    if (d->dim == 3) sz_max = std::max(sz_max, abs(p.n[2]));
+  }
+  const int max_shift = std::max(sx_max, std::max(sy_max, sz_max));
+  if (max_shift > 16) {
+    set_err(err, errlen, "displacements above 16 lattice sites are not supported");
+    return RLBM_EINVAL;
+  }
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->q3 = np;
+    info->q = Q;
+    info->v0 = (double)v0;
+    info->v0_lo = (double)wlo;
+    info->v0_hi = (double)whi;
+    for (int g = 0; g < 11; ++g) info->weights[g] = (double)w[g];
+    info->ortho_residual = (double)res;
+    info->max_shift = max_shift;
+    info->cond = (double)cond;
+  }
+  if (!tab) return RLBM_OK;
+
+  memset(tab, 0, sizeof(*tab));
+  RlbmConsts& c = tab->c;
+  c.Q = Q;
+  c.order = 3;
+  c.dim = d->dim;
+  c.precision = d->precision;
+  c.max_shift = max_shift;
+  c.sx_max = sx_max;
+  c.sy_max = sy_max;
+  c.sz_max = sz_max;
+  c.zeta = d->zeta;
+  c.inv_zeta = (double)(1.0L / m);
+  c.v0 = (double)v0;
+  c.n_ref = 1.0;
+  c.T_ref = 1.0;
+  c.o3_c = (double)c0;
+  c.o3_is0 = (double)(1.0L / s0);
+  c.o3_isp = (double)(1.0L / sp);
+  for (int j = 0; j < Q; ++j) {
+    const P3& p0 = pops[members[j][0]];
+    tab->nx[j] = p0.n[0];
+    tab->ny[j] = d->dim >= 2 ? p0.n[1] : 0;
+    tab->nz[j] = d->dim == 3 ? p0.n[2] : 0;
+    tab->dnx[j] = tab->nx[j];
+    tab->dny[j] = tab->ny[j];
+    tab->p0[j] = (double)p0.p[0];
+    tab->px[j] = (double)p0.p[1];
+    tab->py[j] = d->dim >= 2 ? (double)p0.p[2] : 0.0;
+    tab->pz[j] = d->dim == 3 ? (double)p0.p[3] : 0.0;
+    // equilibrium row in the q basis: sum over the class of w_i L^-T J(p_i)
+    ld row[RLBM_NO3] = {};
+    for (int i : members[j]) {
+      ld y[RLBM_NO3];
+      upper_solve(J[i].data(), y);
+      for (int r = 0; r < RLBM_NO3; ++r) row[r] += w[pops[i].g] * y[r];
+    }
+    for (int r = 0; r < RLBM_NO3; ++r) tab->rowo3[j][r] = (double)row[r];
+    tab->rowo3[j][RLBM_RO3_NX] = tab->nx[j];
+    tab->rowo3[j][RLBM_RO3_NY] = tab->ny[j];
+    tab->rowo3[j][RLBM_RO3_NZ] = tab->nz[j];
+    // moment rows of the 3D kernels.  The members of a merged class carry
+    // equal populations (the flow has no velocity along the merged axes and
+    // does not vary along them), so odd moments in the merged components
+    // cancel over the class and its squared components enter as the members'
+    // mean
+    const ld px = p0.p[1], py = d->dim >= 2 ? p0.p[2] : 0.0L, pz = d->dim == 3 ? p0.p[3] : 0.0L;
+    const ld e = p0.p[0];
+    ld pyy = 0, pzz = 0;
+    for (int i : members[j]) {
+      pyy += pops[i].p[2] * pops[i].p[2];
+      pzz += pops[i].p[3] * pops[i].p[3];
+    }
+    pyy /= (ld)members[j].size();
+    pzz /= (ld)members[j].size();
+    const ld mono[RLBM_NB3] = {e,      px,      py,      pz,      e * e,   e * px, e * py,
+                               e * pz, px * px, px * py, px * pz, pyy,     py * pz, pzz};
+    for (int a = 0; a < RLBM_NB3; ++a) tab->rowm3d[j][a] = (double)mono[a];
+  }
+  return RLBM_OK;
+}
+
 int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTable* tab, char* err,
                      size_t errlen) {
-  if (!d || !d->group_base || d->n_groups != 6 || !(d->zeta > 0) || d->dim < 1 || d->dim > 3 ||
-      d->precision < RLBM_FP64 || d->precision > RLBM_FP16_DEV) {
-    set_err(err, errlen, "invalid stencil description (second order needs 6 groups, zeta > 0, dim 1|2|3)");
+  if (!d || !d->group_base || !(d->zeta > 0) || d->dim < 1 || d->dim > 3 || d->precision < RLBM_FP64 ||
+      d->precision > RLBM_FP16_DEV || !(d->order == 0 || d->order == 2 || d->order == 3) ||
+      d->n_groups != (d->order == 3 ? 11 : 6)) {
+    set_err(err, errlen,
+            "invalid stencil description (order 2: 6 groups, order 3: 11 groups; zeta > 0; dim 1|2|3)");
     return RLBM_EINVAL;
   }
   for (int i = 0; i < 3 * d->n_groups; ++i)
@@ -286,6 +789,7 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
       set_err(err, errlen, "group base components must be in [0, 64]");
       return RLBM_EINVAL;
     }
+  if (d->order == 3) return build_table_o3(d, info, tab, err, errlen);
   Stencil st((ld)d->zeta, d->n_groups, d->group_base);
   for (int g = 0; g < 6; ++g)
     for (int h = g + 1; h < 6; ++h)
@@ -296,99 +800,13 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
 
   ld v0 = d->v0;
   ld wlo = 0, whi = 0;
+  if (d->weights && !(v0 > 0)) {
+    set_err(err, errlen, "given weights need a given v0");
+    return RLBM_EINVAL;
+  }
   if (!(v0 > 0)) {
-    // search the interval of all-positive weights: grid, zoom on max min_k w_k, bisect edges
-    ld lo = d->v0_lo > 0 ? (ld)d->v0_lo : 1e-6L;
-    ld hi = d->v0_hi > 0 ? std::min((ld)d->v0_hi, st.vmax * (1 - 1e-12L)) : st.vmax * (1 - 1e-12L);
-    if (!(hi > lo)) {
-      set_err(err, errlen, "empty v0 search interval");
-      return RLBM_EINVAL;
-    }
-    const int G = 400;
-    ld a = lo, b = hi, best = lo, bestv = -1e300L;
-    for (int zoom = 0; zoom < 14 && bestv <= 0; ++zoom) {
-      ld step = (b - a) / G;
-      for (int i = 0; i <= G; ++i) {
-        ld v = a + step * i;
-        ld mw = st.min_weight(v);
-        if (mw > bestv) {
-          bestv = mw;
-          best = v;
-        }
-      }
-      a = std::max(best - 2 * step, lo);
-      b = std::min(best + 2 * step, hi);
-    }
-    if (!(bestv > 0)) {
-      set_err(err, errlen, "no v0 with all weights positive in the search interval");
-      return RLBM_ENOSTENCIL;
-    }
-    // bracket each edge by steps that double from the last grid spacing (after
-    // deep zooming that spacing can be far below the window's width), then bisect
-    const ld step0 = std::max((b - a) / G, (hi - lo) * 1e-15L);
-    ld l_in = best, l_out = lo, r_in = best, r_out = hi;
-    for (ld s = step0; best - s > lo; s *= 2) {
-      if (st.min_weight(best - s) > 0) {
-        l_in = best - s;
-      } else {
-        l_out = best - s;
-        break;
-      }
-    }
-    for (ld s = step0; best + s < hi; s *= 2) {
-      if (st.min_weight(best + s) > 0) {
-        r_in = best + s;
-      } else {
-        r_out = best + s;
-        break;
-      }
-    }
-    auto bisect = [&st](ld& in, ld& out) {
-      for (int it = 0; it < 100; ++it) {
-        const ld mid = 0.5L * (in + out);
-        if (st.min_weight(mid) > 0) in = mid; else out = mid;
-      }
-    };
-    bisect(l_in, l_out);
-    bisect(r_in, r_out);
-    // A doubled step can jump over a run of negative weights into another
-    // positive run; the window must be the run that holds `best`.  Sample it:
-    // if any interior point is not positive, walk out from `best` at the
-    // finest spacing instead (bounded), and bisect from there.
-    auto connected = [&st](ld x0, ld x1) {
-      for (int i = 1; i < 64; ++i)
-        if (!(st.min_weight(x0 + (x1 - x0) * i / 64) > 0)) return false;
-      return true;
-    };
-    if (!connected(l_in, best) || !connected(best, r_in)) {
-      // (a walk that ends without leaving the run keeps its last point as the
-      // edge: out == in leaves nothing to bisect)
-      l_in = best, r_in = best;
-      l_out = lo, r_out = hi;
-      bool l_found = false, r_found = false;
-      for (int i = 1; i <= 100000 && best - i * step0 > lo; ++i) {
-        if (st.min_weight(best - i * step0) > 0) {
-          l_in = best - i * step0;
-        } else {
-          l_out = best - i * step0;
-          l_found = true;
-          break;
-        }
-      }
-      for (int i = 1; i <= 100000 && best + i * step0 < hi; ++i) {
-        if (st.min_weight(best + i * step0) > 0) {
-          r_in = best + i * step0;
-        } else {
-          r_out = best + i * step0;
-          r_found = true;
-          break;
-        }
-      }
-      if (l_found) bisect(l_in, l_out);
-      if (r_found) bisect(r_in, r_out);
-    }
-    wlo = l_in;
-    whi = r_in;
+    const int rc = positive_window([&st](ld v) { return st.min_weight(v); }, st.vmax, d, wlo, whi, err, errlen);
+    if (rc) return rc;
     v0 = 0.5L * (wlo + whi);
   }
   if (!(v0 < st.vmax)) {
@@ -396,7 +814,9 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
     return RLBM_EINVAL;
   }
   std::vector<ld> w;
-  if (!st.weights(v0, w)) {
+  if (d->weights) {
+    for (int g = 0; g < 6; ++g) w.push_back((ld)d->weights[g]);
+  } else if (!st.weights(v0, w)) {
     set_err(err, errlen, "singular quadrature system for this group set");
     return RLBM_ENOSTENCIL;
   }
@@ -496,6 +916,7 @@ int rlbm_build_table(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTa
   memset(tab, 0, sizeof(*tab));
   RlbmConsts& c = tab->c;
   c.Q = Q;
+  c.order = 2;
   c.dim = d->dim;
   c.precision = d->precision;
   c.max_shift = max_shift;

@@ -3,7 +3,7 @@
 #pragma once
 #include <stdint.h>
 
-#define RLBM_QMAX 160   // population classes per stencil (6 groups: <= 150)
+#define RLBM_QMAX 192   // population classes per stencil (6 groups: <= 150; 11 groups: more)
 #define RLBM_NB 10      // second-order polynomials that survive U_z = 0
 
 // Inverse equation of state T(u), u = eps/n - mbar (kinetic energy per
@@ -34,6 +34,56 @@ enum { RLBM_R_NX = 10, RLBM_R_NY = 11, RLBM_R_INVSCALE = 12 };
 enum { RLBM_R3_NX = 14, RLBM_R3_NY = 15, RLBM_R3_NZ = 16, RLBM_R3_INVSCALE = 17 };
 #define RLBM_RM3_SCALE 14
 
+// Third-order model (Sec. III.A: 30 polynomials of degree <= 3, float64
+// only).  With M_m = int f^eq p^{i1} .. p^{ir} d^3p/p^0 (a component of a
+// Maxwell-Juttner moment tensor of rank r <= 3, density included) for the 30
+// monomials listed in kO3Idx, and q_m the centred, scaled monomials
+// ((p0 - c)/s0)^k0 (p_x/sp)^kx (p_y/sp)^ky (p_z/sp)^kz of the same
+// exponents, the equilibrium of population j is sum_m R_jm a_m with
+// a_m = int f^eq q_m d^3p/p^0 (a binomial combination of the M's) and the
+// row R_j built on the host in the q basis (well conditioned at every mbar).
+// Rows: [R_j0 .. R_j29, n_x, n_y, n_z, 0].
+#define RLBM_NO3 30
+#define RLBM_ROWO3 34
+enum { RLBM_RO3_NX = 30, RLBM_RO3_NY = 31, RLBM_RO3_NZ = 32 };
+// index lists (0 = time component, 1..3 = x, y, z; -1 = unused) of the 30
+// monomials: degree 0, 1, 2 and 3, p_z at most once (on the mass shell the
+// monomials with p_z^2 or p_z^3 depend on these)
+static constexpr signed char kO3Idx[RLBM_NO3][3] = {
+    {-1, -1, -1},                                                                     // 1
+    {0, -1, -1}, {1, -1, -1}, {2, -1, -1}, {3, -1, -1},                               // p^a
+    {0, 0, -1}, {0, 1, -1}, {0, 2, -1}, {0, 3, -1}, {1, 1, -1}, {1, 2, -1},           // p^a p^b
+    {1, 3, -1}, {2, 2, -1}, {2, 3, -1},
+    {0, 0, 0}, {0, 0, 1}, {0, 0, 2}, {0, 0, 3}, {0, 1, 1}, {0, 1, 2}, {0, 1, 3},      // p^a p^b p^c
+    {0, 2, 2}, {0, 2, 3}, {1, 1, 1}, {1, 1, 2}, {1, 1, 3}, {1, 2, 2}, {1, 2, 3},
+    {2, 2, 2}, {2, 2, 3}};
+
+// exponent of axis `ax` (0 = time) in monomial m
+constexpr int o3_exp(int m, int ax) {
+  int e = 0;
+  for (int r = 0; r < 3; ++r) e += kO3Idx[m][r] == ax ? 1 : 0;
+  return e;
+}
+// kO3Raw.r[m][k]: index of the monomial p0^k times the spatial part of
+// monomial m (k <= o3_exp(m, 0)), -1 beyond
+struct O3Raw {
+  signed char r[RLBM_NO3][4];
+};
+constexpr O3Raw make_o3_raw() {
+  O3Raw t{};
+  for (int m = 0; m < RLBM_NO3; ++m)
+    for (int k = 0; k < 4; ++k) {
+      t.r[m][k] = -1;
+      if (k > o3_exp(m, 0)) continue;
+      for (int q = 0; q < RLBM_NO3; ++q)
+        if (o3_exp(q, 0) == k && o3_exp(q, 1) == o3_exp(m, 1) && o3_exp(q, 2) == o3_exp(m, 2) &&
+            o3_exp(q, 3) == o3_exp(m, 3))
+          t.r[m][k] = (signed char)q;
+    }
+  return t;
+}
+static constexpr O3Raw kO3Raw = make_o3_raw();
+
 #define RLBM_LANDAU_NEWTON 0      // Newton on det(lambda I - T eta) from lambda = T^00
 #define RLBM_LANDAU_FIXED_POINT 1 // eps = T^00 - T^0i u_i, u_i = (T^0i - T^ij u_j)/eps
 
@@ -45,6 +95,7 @@ enum { RLBM_R3_NX = 14, RLBM_R3_NY = 15, RLBM_R3_NZ = 16, RLBM_R3_INVSCALE = 17 
 
 struct RlbmConsts {
   int Q;          // population classes (planes)
+  int order;      // 2 or 3 (equilibrium expansion order)
   int dim;        // 1, 2 or 3
   int precision;  // RLBM_FP64 / RLBM_FP32_DEV / RLBM_FP16_DEV
   int max_shift;
@@ -65,6 +116,7 @@ struct RlbmConsts {
   double ref_mom[9];       // sum_j f^ref_j (p0, px, py, p0p0, p0px, p0py, pxpx, pxpy, pypy)
   double nb_ref3[RLBM_NB3];  // 3D: n_ref * b_k(rest, T_ref) for all 14 polynomials
   double ref_mom3[RLBM_NB3]; // 3D: sum_j f^ref_j times the 14 monomials of the 3D moment rows
+  double o3_c, o3_is0, o3_isp;  // third order: centre c of p0, 1/s0, 1/sp of the q basis
 };
 
 struct RlbmTable {
@@ -110,6 +162,9 @@ struct RlbmTable {
   // storage the step writes), [QMAX, 2 QMAX) pulled.  Written on the device
   // by rlbm_init_fields for the lattice in use.
   unsigned offs[2 * RLBM_QMAX] __attribute__((aligned(64)));
+  // third-order equilibrium rows (layout above; classes of dim 1 and 2 carry
+  // the sums over their members and n_z = 0)
+  double rowo3[RLBM_QMAX][RLBM_ROWO3] __attribute__((aligned(64)));
 };
 
 // Per-block health / statistics slot, accumulated by the step kernel.

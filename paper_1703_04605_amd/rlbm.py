@@ -51,7 +51,8 @@ class StencilDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("n_groups", ctypes.c_int),
                 ("group_base", ctypes.POINTER(ctypes.c_int)), ("zeta", ctypes.c_double),
                 ("v0", ctypes.c_double), ("v0_lo", ctypes.c_double), ("v0_hi", ctypes.c_double),
-                ("precision", ctypes.c_int), ("n_ref", ctypes.c_double), ("T_ref", ctypes.c_double)]
+                ("precision", ctypes.c_int), ("n_ref", ctypes.c_double), ("T_ref", ctypes.c_double),
+                ("order", ctypes.c_int), ("weights", ctypes.POINTER(ctypes.c_double))]
 
 
 class StencilInfo(ctypes.Structure):
@@ -149,12 +150,15 @@ def _check(rc, ctx=None):
         raise RlbmError(rc, msg.decode() if msg else "")
 
 
-def make_desc(bases, zeta, v0=0.0, dim=2, precision="fp64", n_ref=1.0, T_ref=1.0, v0_lo=0.0, v0_hi=0.0):
+def make_desc(bases, zeta, v0=0.0, dim=2, precision="fp64", n_ref=1.0, T_ref=1.0, v0_lo=0.0, v0_hi=0.0,
+              order=2, weights=None):
     flat = [int(c) for b in bases for c in b]
     arr = (ctypes.c_int * len(flat))(*flat)
+    warr = None if weights is None else (ctypes.c_double * len(weights))(*[float(w) for w in weights])
     d = StencilDesc(dim, len(bases), ctypes.cast(arr, ctypes.POINTER(ctypes.c_int)), float(zeta), float(v0),
-                    float(v0_lo), float(v0_hi), PRECISION[precision], float(n_ref), float(T_ref))
-    d._keep = arr
+                    float(v0_lo), float(v0_hi), PRECISION[precision], float(n_ref), float(T_ref), int(order),
+                    None if warr is None else ctypes.cast(warr, ctypes.POINTER(ctypes.c_double)))
+    d._keep = (arr, warr)
     return d
 
 
@@ -174,18 +178,19 @@ def check_lattice(bases, zeta, v0, nx, ny, dim=2, precision="fp64", **lattice):
     _check(lib().rlbm_check_lattice(ctypes.byref(d), ctypes.byref(lat)))
 
 
-def info_dict(info):
+def info_dict(info, ngroups=6):
     return {"q3": info.q3, "q": info.q, "v0": info.v0, "v0_lo": info.v0_lo, "v0_hi": info.v0_hi,
-            "weights": [info.weights[i] for i in range(6)], "ortho_residual": info.ortho_residual,
+            "weights": [info.weights[i] for i in range(ngroups)], "ortho_residual": info.ortho_residual,
             "max_shift": info.max_shift, "cond": info.cond}
 
 
-def solve_stencil(bases, zeta, v0=0.0, dim=2, v0_lo=0.0, v0_hi=0.0):
-    """Host-only stencil construction (no GPU): dict of the stencil info."""
-    d = make_desc(bases, zeta, v0, dim, "fp64", v0_lo=v0_lo, v0_hi=v0_hi)
+def solve_stencil(bases, zeta, v0=0.0, dim=2, v0_lo=0.0, v0_hi=0.0, order=2, weights=None):
+    """Host-only stencil construction (no GPU): dict of the stencil info
+    (order 2: six groups; order 3: eleven)."""
+    d = make_desc(bases, zeta, v0, dim, "fp64", v0_lo=v0_lo, v0_hi=v0_hi, order=order, weights=weights)
     info = StencilInfo()
     _check(lib().rlbm_solve_stencil(ctypes.byref(d), ctypes.byref(info)))
-    return info_dict(info)
+    return info_dict(info, len(bases))
 
 
 def class_table(bases, zeta, v0, dim=2):
@@ -272,17 +277,19 @@ class Solver:
     bases: group base vectors; zeta = m/T_R; v0 (<= 0: search the positive
     window); precision 'fp64' | 'fp32' | 'fp16' (deviation storage)."""
 
-    def __init__(self, bases, zeta, v0, dim=2, precision="fp64", n_ref=1.0, T_ref=1.0, v0_lo=0.0, v0_hi=0.0):
+    def __init__(self, bases, zeta, v0, dim=2, precision="fp64", n_ref=1.0, T_ref=1.0, v0_lo=0.0, v0_hi=0.0,
+                 order=2, weights=None):
         import torch
         self.torch = torch
         self.precision = precision
         self.dim = dim
-        self._desc = make_desc(bases, zeta, v0, dim, precision, n_ref, T_ref, v0_lo, v0_hi)
+        self.order = order
+        self._desc = make_desc(bases, zeta, v0, dim, precision, n_ref, T_ref, v0_lo, v0_hi, order, weights)
         info = StencilInfo()
         ctx = ctypes.c_void_p()
         _check(lib().rlbm_init_stencil(ctypes.byref(ctx), ctypes.byref(self._desc), ctypes.byref(info)))
         self.ctx = ctx
-        self.info = info_dict(info)
+        self.info = info_dict(info, len(bases))
         self.nx = self.ny = None
         self.pop = None
 
@@ -409,12 +416,16 @@ def device_copy(dst, src, workgroups=2048):
 
 
 class Solver3D(Solver):
-    """A 3D lattice (Nx x Ny x Nz, every population of the stencil) on the
-    current device; fields are CUDA float64 tensors [nz, ny, nx]."""
+    """A lattice on the 3D layout on the current device; fields are CUDA
+    float64 tensors [nz, ny, nx].  Second order: dim 3 (Nx x Ny x Nz, every
+    population of the stencil).  Third order (order=3, eleven groups, float64):
+    dim 3, or dim 2 / 1 with merged classes on an Nx x Ny x 1 / Nx x 1 x 1
+    lattice."""
 
-    def __init__(self, bases, zeta, v0, precision="fp64", n_ref=1.0, T_ref=1.0, v0_lo=0.0, v0_hi=0.0):
-        super().__init__(bases, zeta, v0, dim=3, precision=precision, n_ref=n_ref, T_ref=T_ref, v0_lo=v0_lo,
-                         v0_hi=v0_hi)
+    def __init__(self, bases, zeta, v0, precision="fp64", n_ref=1.0, T_ref=1.0, v0_lo=0.0, v0_hi=0.0,
+                 order=2, dim=3, weights=None):
+        super().__init__(bases, zeta, v0, dim=dim, precision=precision, n_ref=n_ref, T_ref=T_ref, v0_lo=v0_lo,
+                         v0_hi=v0_hi, order=order, weights=weights)
         self.nz = None
 
     def population_bytes3(self, nx, ny, nz):

@@ -1,0 +1,173 @@
+"""Third-order model on the GPU (float64, the 3D layout for every
+dimension) against the oracle's third-order lattice models: the paper's
+third-order stencil (Fig. 2b: groups G1, G2, G3, G4, G5, G8, G9, G10, G12,
+G13, G15, 161 populations) at mbar = 7.5, where its weights are positive.
+
+Both sides use the oracle's weights (passed to the library), so the
+comparison isolates the step; the library's own quadrature solve is checked
+against the oracle on the host (test_host_library)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+G3 = [1, 2, 3, 4, 5, 8, 9, 10, 12, 13, 15]
+MBAR, V0 = 7.5, 0.24829287991167
+FIELDS = ("n", "eps", "T", "P", "ux", "uy", "uz")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from oracle import groups, third_order as t3
+    bases = groups.bases_of(G3)
+    w, res = t3.weights(bases, MBAR, V0, dps=40)
+    assert float(res) < 1e-30
+    return bases, [float(x) for x in w]
+
+
+def smooth(nz, ny, nx, seed, umax=0.25, vary_z=True):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    z, y, x = np.meshgrid(np.arange(nz) / nz, np.arange(ny) / ny, np.arange(nx) / nx, indexing="ij")
+
+    def field(amp):
+        f = np.zeros((nz, ny, nx))
+        for _ in range(3):
+            k = rng.integers(0, 3, 3)
+            if not vary_z:
+                k[0] = 0
+            f += amp * rng.uniform(-1, 1) * np.cos(2 * np.pi * (k[0] * z + k[1] * y + k[2] * x) + rng.uniform(0, 6.3))
+        return f
+
+    return 1.0 + field(0.1), 1.0 + field(0.1), field(umax / 3), field(umax / 3), field(umax / 3)
+
+
+def gpu(bases, w, fields, steps, dim, bc, tau=0.9):
+    from paper_1703_04605_amd import rlbm
+    from tests.helpers import to_dev
+    s = rlbm.Solver3D(bases, MBAR, V0, order=3, dim=dim, weights=w)
+    s.init_fields(*to_dev(fields), bc=bc, tau=tau)
+    s.step(steps)
+    out = {k: v.cpu().numpy() for k, v in s.moments(raw=True).items()}
+    h = s.health()
+    info = s.info
+    del s
+    return out, h, info
+
+
+def errs(a, b, keys):
+    """max |a - b| / max |b| per field; velocity components are scaled by the
+    largest speed component of the reference (a component whose own maximum
+    is tiny, e.g. 1.4e-3 against 3e-2 for the other, would otherwise turn its
+    rounding floor into 5e-12: the oracle itself moves that much when its
+    populations are perturbed by one ulp)."""
+    vel = [k for k in ("ux", "uy", "uz") if k in b]
+    vmax = max(np.abs(b[k]).max() for k in vel) if vel else 1.0
+    return {k: float(np.abs(a[k] - b[k]).max() / (vmax if k in vel else np.abs(b[k]).max())) for k in keys}
+
+
+@pytest.mark.parametrize("bc", [("periodic", "periodic", "periodic"), ("outflow", "periodic", "outflow")])
+def test_third_order_3d_vs_oracle(setup, bc):
+    """70 x 5 x 4 (two 64-site tiles per row, the second ragged), 4 steps,
+    every population of the stencil."""
+    from oracle import lattice as L
+    bases, w = setup
+    fields = smooth(4, 5, 70, seed=21)
+    g, h, info = gpu(bases, w, fields, 4, 3, bc)
+    assert info["q"] == 161 and h["flags"] == 0, (info, h)
+    ps = L.build_stencil(bases, MBAR, V0, mode="full", order=3, weights=w)
+    m = L.Model3D(ps, 70, 5, 4, bc=bc, tau=0.9)
+    m.init_equilibrium(*fields)
+    m.step(4)
+    r = m.fields()
+    e = errs(g, r, FIELDS)
+    print(e)
+    assert max(e.values()) < 1e-12, e
+    assert np.abs(g["raw14"] - r["raw14"]).max() < 1e-12 * np.abs(r["raw14"]).max()
+
+
+@pytest.mark.parametrize("bc", [("periodic", "periodic"), ("outflow", "outflow")])
+def test_third_order_2d_classes_vs_oracle_full(setup, bc):
+    """dim 2 (95 merged classes on an Nx x Ny x 1 lattice) against the
+    oracle's full 161-population stencil on the same 1-thick slab."""
+    from oracle import lattice as L
+    bases, w = setup
+    n, T, ux, uy, _ = smooth(1, 6, 70, seed=22, vary_z=False)
+    uz = np.zeros_like(n)
+    g, h, info = gpu(bases, w, (n, T, ux, uy, uz), 6, 2, bc + ("periodic",))
+    assert info["q"] == 95 and h["flags"] == 0, (info, h)
+    ps = L.build_stencil(bases, MBAR, V0, mode="full", order=3, weights=w)
+    m = L.Model3D(ps, 70, 6, 1, bc=bc + ("periodic",), tau=0.9)
+    m.init_equilibrium(n, T, ux, uy, uz)
+    m.step(6)
+    r = m.fields()
+    e = errs(g, r, ("n", "eps", "T", "P", "ux", "uy"))
+    print(e)
+    assert max(e.values()) < 1e-12, e
+    assert np.abs(g["uz"]).max() < 1e-15
+
+
+def test_third_order_1d_shock_tube_vs_oracle(setup):
+    """dim 1 (36 classes): a pressure step between outflow ends, 40 steps,
+    against the oracle's 1D projected third-order model."""
+    from oracle import lattice as L
+    bases, w = setup
+    nx = 150
+    x = np.arange(nx)
+    n = np.where(x < nx // 2, 1.0, 0.6)[None, None, :]
+    T = np.where(x < nx // 2, 1.0, 0.8)[None, None, :]
+    z = np.zeros_like(n)
+    g, h, info = gpu(bases, w, (n, T, z, z, z), 40, 1, ("outflow", "periodic", "periodic"), tau=0.8)
+    assert info["q"] == 36 and h["flags"] == 0, (info, h)
+    ps = L.build_stencil(bases, MBAR, V0, mode="projected", dim=1, order=3, weights=w)
+    m = L.Model(ps, nx, 1, bc=("outflow", "periodic"), tau=0.8)
+    m.init_equilibrium(n[0], T[0], z[0], z[0])
+    m.step(40)
+    r = m.fields()
+    e = errs({k: g[k][0] for k in ("n", "eps", "T", "P", "ux")}, r, ("n", "eps", "T", "P", "ux"))
+    print(e)
+    assert np.abs(r["ux"]).max() > 0.01
+    assert max(e.values()) < 1e-12, e
+
+
+def test_third_order_conservation_and_fixed_point(setup):
+    from tests.helpers import to_dev
+    from paper_1703_04605_amd import rlbm
+    bases, w = setup
+    fields = smooth(1, 16, 96, seed=23, vary_z=False)
+    fields = fields[:4] + (np.zeros_like(fields[0]),)
+    g0, _, _ = gpu(bases, w, fields, 0, 2, ("periodic",) * 3)
+    g1, h, _ = gpu(bases, w, fields, 50, 2, ("periodic",) * 3)
+    assert h["flags"] == 0
+    t0, t1 = g0["raw14"].sum(axis=(1, 2, 3)), g1["raw14"].sum(axis=(1, 2, 3))
+    for k in (0, 4, 5, 6):
+        assert abs(t1[k] - t0[k]) < 1e-12 * abs(t0[4]), k
+    u = np.ones((1, 8, 70))
+    s = rlbm.Solver3D(bases, MBAR, V0, order=3, dim=2, weights=w)
+    s.init_fields(*to_dev((1.1 * u, 0.95 * u, 0.15 * u, -0.2 * u, 0 * u)), tau=0.9)
+    a = {k: v.cpu().numpy() for k, v in s.moments().items()}
+    s.step(5)
+    b = {k: v.cpu().numpy() for k, v in s.moments().items()}
+    for k in ("n", "T", "ux", "uy"):
+        assert np.abs(a[k] - b[k]).max() < 1e-13, k
+
+
+def test_third_order_entry_points():
+    """Third-order stencils take the 3D entry points at every dimension and
+    float64 storage only."""
+    from oracle import groups
+    from paper_1703_04605_amd import rlbm
+    bases = groups.bases_of(G3)
+    with pytest.raises(rlbm.RlbmError):
+        rlbm.Solver3D(bases, MBAR, V0, order=3, dim=2, precision="fp32")
+    s = rlbm.Solver3D(bases, MBAR, V0, order=3, dim=2)
+    assert s.population_bytes(16, 8) == 0
+    assert s.population_bytes3(16, 8, 1) > 0 and s.population_bytes3(16, 8, 2) == 0
+    L = rlbm.lib()
+    assert L.rlbm_population_bytes3(s.ctx, 16, 8, 1) > 0

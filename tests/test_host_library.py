@@ -176,3 +176,45 @@ def test_3d_stencil_and_lattice_checks_on_the_host():
     lat = rlbm.lattice_desc(1024, 1024)
     lat.nz = 1024          # 2^30 sites but far more than 2^31 stored elements
     assert L.rlbm_check_lattice(d3, lat) == rlbm.RLBM_EINVAL
+
+
+def test_third_order_quadrature_matches_oracle():
+    """Third order (Sec. III.D, eleven conditions) on the paper's
+    161-population stencil at mbar = 7.5: the library's window, weights and
+    orthonormality against the oracle's 465 pair conditions.  The weights
+    agree to the conditioning of the problem (cond ~3e5 times the moment
+    integrals' ~1e-17), not to the last bit."""
+    import numpy as np
+    from oracle import groups, third_order as t3
+    bases = groups.bases_of([1, 2, 3, 4, 5, 8, 9, 10, 12, 13, 15])
+    infos = {dim: rlbm.solve_stencil(bases, 7.5, 0.0, dim=dim, order=3) for dim in (1, 2, 3)}
+    assert [infos[d]["q"] for d in (1, 2, 3)] == [36, 95, 161]
+    i = infos[3]
+    assert i["q3"] == 161 and i["ortho_residual"] < 1e-12
+    w, res = t3.weights(bases, 7.5, i["v0"], dps=40)
+    w = np.array([float(x) for x in w])
+    assert float(res) < 1e-30
+    assert (np.abs(w - np.array(i["weights"])) < 1e-10 * w).all()
+    # the window's edges: positive just inside, not just outside (oracle)
+    for edge, sgn in ((i["v0_lo"], 1), (i["v0_hi"], -1)):
+        assert t3.min_weight(bases, 7.5, edge + sgn * 1e-9, dps=30) > 0
+        assert t3.min_weight(bases, 7.5, edge - sgn * 1e-9, dps=30) < 0
+    # the paper's second-order example stencil cannot be a third-order one
+    with pytest.raises(rlbm.RlbmError):
+        rlbm.solve_stencil(groups.bases_of([1, 2, 3, 4, 5, 6]), 5.0, 0.0, order=3)
+
+
+def test_given_weights_are_checked():
+    """desc.weights replaces the solve; wrong weights fail the
+    orthonormality check, and weights need a given v0."""
+    from oracle import groups
+    bases = groups.bases_of([1, 2, 3, 4, 5, 6])
+    ref = rlbm.solve_stencil(bases, 5.0, 0.398)
+    got = rlbm.solve_stencil(bases, 5.0, 0.398, weights=ref["weights"])
+    assert got["weights"] == ref["weights"] and got["ortho_residual"] < 1e-12
+    bad = list(ref["weights"])
+    bad[2] *= 1.001
+    with pytest.raises(rlbm.RlbmError):
+        rlbm.solve_stencil(bases, 5.0, 0.398, weights=bad)
+    with pytest.raises(rlbm.RlbmError):
+        rlbm.solve_stencil(bases, 5.0, 0.0, weights=ref["weights"])

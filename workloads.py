@@ -52,6 +52,14 @@ def riemann_1d(nx=800):
     return (n, T, z, z.copy()), tau
 
 
+# Third-order model: the paper's third-order stencil (Fig. 2b; groups G1,
+# G2, G3, G4, G5, G8, G9, G10, G12, G13, G15, 161 populations) at mbar = 7.5,
+# inside the range where its eleven weights are all positive (about 6.5-8.2);
+# v0 is the middle of the positive window the library finds.
+THIRD_ORDER = {"bases": [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 1, 1), (2, 0, 0), (2, 1, 1), (2, 2, 1), (2, 2, 2),
+                         (3, 1, 0), (3, 2, 0), (3, 1, 1)], "zeta": 7.5}
+
+
 def taylor_green(nx, ny, seed=0, umax=0.3, noise=0.01):
     """Periodic Taylor-Green-type vortex with peak speed umax, plus 1%
     Gaussian noise on n and T around n = T = 1."""
