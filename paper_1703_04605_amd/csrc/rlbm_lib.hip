@@ -889,6 +889,8 @@ k_step3(RlbmStepArgs a) {
 // the population's row (eq. mj-projected-distribution at N = 3), relaxes and
 // stores.  No
 // population stays in registers, so any class count fits.
+constexpr int kO3Chunk = 16;
+
 __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
   typedef const __attribute__((address_space(4))) unsigned* OffPtr;
   const TabPtr tb = as_tab(a.tab);
@@ -915,13 +917,25 @@ __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
   const OffPtr pull = (OffPtr)a.offs;
   const OffPtr own = (OffPtr)a.offs_st;
 
+  // populations go in chunks of kO3Chunk: all pulls of a chunk are issued
+  // before the first is used (a class-by-class loop would wait out one
+  // memory round trip per class); the last chunk re-reads class Q - 1
   double m[RLBM_NB3];
 #pragma unroll
   for (int k = 0; k < RLBM_NB3; ++k) m[k] = 0.0;
-  for (int j = 0; j < Q; ++j) {
-    const double f = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs_ld, vld, pull[j], 0));
+  for (int j0 = 0; j0 < Q; j0 += kO3Chunk) {
+    double f[kO3Chunk];
 #pragma unroll
-    for (int k = 0; k < RLBM_NB3; ++k) m[k] = fma(f, tb->rowm3d[j][k], m[k]);
+    for (int i = 0; i < kO3Chunk; ++i)
+      f[i] = __builtin_bit_cast(double,
+                                __builtin_amdgcn_raw_buffer_load_b64(rs_ld, vld, pull[min(j0 + i, Q - 1)], 0));
+#pragma unroll
+    for (int i = 0; i < kO3Chunk; ++i) {
+      const int j = min(j0 + i, Q - 1);
+      const double fi = j0 + i < Q ? f[i] : 0.0;
+#pragma unroll
+      for (int k = 0; k < RLBM_NB3; ++k) m[k] = fma(fi, tb->rowm3d[j][k], m[k]);
+    }
   }
 
   // Landau frame, density, EOS
@@ -951,16 +965,25 @@ __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
   const bool ghosts = xedge || ym != 0u || zm != 0u;
   const unsigned xm = xedge ? ghost_mask(x, L.nx, L.Sx, L.bc_x) : 0u;
   double* __restrict__ dst = (double*)a.dst;
-  for (int j = 0; j < Q; ++j) {
-    const double f = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs_ld, vld, pull[j], 0));
-    const auto& r = tb->rowo3[j];
-    double feq = M[0] * r[0];
+  for (int j0 = 0; j0 < Q; j0 += kO3Chunk) {
+    double f[kO3Chunk];
 #pragma unroll
-    for (int k = 1; k < RLBM_NO3; ++k) feq = fma(M[k], r[k], feq);
-    const double om = fma(WZ, r[RLBM_RO3_NZ], fma(WY, r[RLBM_RO3_NY], fma(WX, r[RLBM_RO3_NX], w0)));
-    const double out = fma(-om, f - feq, f);
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, out), rs_st, vst, own[j], 0);
-    if (ghosts && active) store_ghosts3(dst + (long long)j * L.cs, L, x, y, z, xm, ym, zm, out);
+    for (int i = 0; i < kO3Chunk; ++i)
+      f[i] = __builtin_bit_cast(double,
+                                __builtin_amdgcn_raw_buffer_load_b64(rs_ld, vld, pull[min(j0 + i, Q - 1)], 0));
+#pragma unroll
+    for (int i = 0; i < kO3Chunk; ++i) {
+      const int j = j0 + i;
+      if (j >= Q) break;
+      const auto& r = tb->rowo3[j];
+      double feq = M[0] * r[0];
+#pragma unroll
+      for (int k = 1; k < RLBM_NO3; ++k) feq = fma(M[k], r[k], feq);
+      const double om = fma(WZ, r[RLBM_RO3_NZ], fma(WY, r[RLBM_RO3_NY], fma(WX, r[RLBM_RO3_NX], w0)));
+      const double out = fma(-om, f[i] - feq, f[i]);
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, out), rs_st, vst, own[j], 0);
+      if (ghosts && active) store_ghosts3(dst + (long long)j * L.cs, L, x, y, z, xm, ym, zm, out);
+    }
   }
   wave_stats(a.slots, t, active ? flags : 0u, active ? (unsigned)iters : 0u, active ? (unsigned)iters : 0u);
 }
