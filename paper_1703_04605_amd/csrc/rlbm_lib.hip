@@ -889,8 +889,11 @@ k_step3(RlbmStepArgs a) {
 // the population's row (eq. mj-projected-distribution at N = 3), relaxes and
 // stores.  No
 // population stays in registers, so any class count fits.
-constexpr int kO3Chunk = 16;
+constexpr int kO3Chunk = 8;
 
+// D: the stencil's class dimension (1, 2: merged classes, only the moments
+// and equilibrium terms that can be nonzero; 3: every population)
+template <int D>
 __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
   typedef const __attribute__((address_space(4))) unsigned* OffPtr;
   const TabPtr tb = as_tab(a.tab);
@@ -934,7 +937,10 @@ __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
       const int j = min(j0 + i, Q - 1);
       const double fi = j0 + i < Q ? f[i] : 0.0;
 #pragma unroll
-      for (int k = 0; k < RLBM_NB3; ++k) m[k] = fma(fi, tb->rowm3d[j][k], m[k]);
+      for (int k = 0; k < RLBM_NB3; ++k)
+        if (o3_mom_active(D, k)) m[k] = fma(fi, tb->rowm3d[j][k], m[k]);
+      // (keeps the scalar row loads of later classes from piling up in SGPRs)
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
 
@@ -976,19 +982,24 @@ __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
       const int j = j0 + i;
       if (j >= Q) break;
       const auto& r = tb->rowo3[j];
-      double feq = M[0] * r[0];
+      constexpr O3Act act = kO3Act[D];
+      double feq = M[act.m[0]] * r[0];
 #pragma unroll
-      for (int k = 1; k < RLBM_NO3; ++k) feq = fma(M[k], r[k], feq);
-      const double om = fma(WZ, r[RLBM_RO3_NZ], fma(WY, r[RLBM_RO3_NY], fma(WX, r[RLBM_RO3_NX], w0)));
+      for (int k = 1; k < act.n; ++k) feq = fma(M[act.m[k]], r[k], feq);
+      double om = fma(WX, r[RLBM_RO3_NX], w0);
+      if (D >= 2) om = fma(WY, r[RLBM_RO3_NY], om);
+      if (D == 3) om = fma(WZ, r[RLBM_RO3_NZ], om);
       const double out = fma(-om, f[i] - feq, f[i]);
       __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, out), rs_st, vst, own[j], 0);
       if (ghosts && active) store_ghosts3(dst + (long long)j * L.cs, L, x, y, z, xm, ym, zm, out);
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   wave_stats(a.slots, t, active ? flags : 0u, active ? (unsigned)iters : 0u, active ? (unsigned)iters : 0u);
 }
 
-// f_i(x, 0) = f_i^eq(n, T, u) at third order
+// f_i(x, 0) = f_i^eq(n, T, u) at third order (D as in k_step_o3)
+template <int D>
 __global__ void __launch_bounds__(kBlock) k_init_o3(RlbmInitArgs a, const double* __restrict__ uz) {
   const TabPtr tb = as_tab(a.tab);
   const RlbmLayout& L = a.L;
@@ -1007,9 +1018,11 @@ __global__ void __launch_bounds__(kBlock) k_init_o3(RlbmInitArgs a, const double
   centred_o3(Mr, tb->c.o3_c, tb->c.o3_is0, tb->c.o3_isp, M);
   double* __restrict__ dst = (double*)a.dst;
   const long long o = (long long)(z + L.GZ) * L.zs + (long long)(y + L.GY) * L.rs + x + L.GX;
+  constexpr O3Act act = kO3Act[D];
   for (int j = 0; j < tb->c.Q; ++j) {
     double fe = 0.0;
-    for (int k = 0; k < RLBM_NO3; ++k) fe = fma(M[k], tb->rowo3[j][k], fe);
+#pragma unroll
+    for (int k = 0; k < act.n; ++k) fe = fma(M[act.m[k]], tb->rowo3[j][k], fe);
     dst[(long long)j * L.cs + o] = fe;
   }
 }
@@ -1617,7 +1630,12 @@ static int init_fields_impl(rlbm_ctx* c, const rlbm_lattice_desc* lat, const dou
   long long sites = (long long)lat->nx * lat->ny * nz;
   dim3 grid((unsigned)((sites + kBlock - 1) / kBlock));
   if (k.order == 3) {
-    hipLaunchKernelGGL(k_init_o3, grid, dim3(kBlock), 0, s, ia, uz);
+    if (k.dim == 1)
+      hipLaunchKernelGGL(k_init_o3<1>, grid, dim3(kBlock), 0, s, ia, uz);
+    else if (k.dim == 2)
+      hipLaunchKernelGGL(k_init_o3<2>, grid, dim3(kBlock), 0, s, ia, uz);
+    else
+      hipLaunchKernelGGL(k_init_o3<3>, grid, dim3(kBlock), 0, s, ia, uz);
   } else if (three_d) {
     switch (k.precision) {
       case RLBM_FP64: hipLaunchKernelGGL(k_init3<RLBM_FP64>, grid, dim3(kBlock), 0, s, ia, uz); break;
@@ -1680,7 +1698,8 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   }
   const bool d3 = layout3(c->h_tab->c);
   StepFn fn = (!d3 && c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? fixed_step(c->fixed_id, g) : nullptr;
-  if (!fn && c->h_tab->c.order == 3) fn = k_step_o3;
+  if (!fn && c->h_tab->c.order == 3)
+    fn = c->h_tab->c.dim == 1 ? k_step_o3<1> : c->h_tab->c.dim == 2 ? k_step_o3<2> : k_step_o3<3>;
   if (!fn) fn = d3 ? select_step3(c->h_tab->c.precision, c->h_tab->c.Q) : select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
   if (!fn) return fail(c, RLBM_ESTATE, "no step kernel for this stencil");
   a.tiles_x = c->tiles_x;

@@ -750,7 +750,8 @@ static int build_table_o3(const rlbm_stencil_desc* d, rlbm_stencil_info* info, R
       upper_solve(J[i].data(), y);
       for (int r = 0; r < RLBM_NO3; ++r) row[r] += w[pops[i].g] * y[r];
     }
-    for (int r = 0; r < RLBM_NO3; ++r) tab->rowo3[j][r] = (double)row[r];
+    const O3Act& act = kO3Act[d->dim];
+    for (int r = 0; r < act.n; ++r) tab->rowo3[j][r] = (double)row[(int)act.m[r]];
     tab->rowo3[j][RLBM_RO3_NX] = tab->nx[j];
     tab->rowo3[j][RLBM_RO3_NY] = tab->ny[j];
     tab->rowo3[j][RLBM_RO3_NZ] = tab->nz[j];

@@ -84,6 +84,32 @@ constexpr O3Raw make_o3_raw() {
 }
 static constexpr O3Raw kO3Raw = make_o3_raw();
 
+// Monomials whose moments can be nonzero on a lattice of dimension dim (the
+// flow has no velocity along the merged axes: in 2D the terms odd in p_z
+// vanish, in 1D also those odd in p_y); rows of 1D and 2D classes hold only
+// these coefficients, in kO3Idx order, at the front of the row.
+constexpr bool o3_active(int dim, int m) {
+  return dim == 3 || (o3_exp(m, 3) == 0 && (dim == 2 || o3_exp(m, 2) % 2 == 0));
+}
+struct O3Act {
+  signed char m[RLBM_NO3];
+  int n;
+};
+constexpr O3Act make_o3_act(int dim) {
+  O3Act t{};
+  t.n = 0;
+  for (int m = 0; m < RLBM_NO3; ++m)
+    if (o3_active(dim, m)) t.m[t.n++] = (signed char)m;
+  return t;
+}
+static constexpr O3Act kO3Act[4] = {O3Act{}, make_o3_act(1), make_o3_act(2), make_o3_act(3)};
+// moments (3D moment-row order) that can be nonzero on a lattice of dimension dim
+constexpr bool o3_mom_active(int dim, int k) {
+  // 0 N0, 1 Nx, 2 Ny, 3 Nz, 4 T00, 5 T0x, 6 T0y, 7 T0z, 8 Txx, 9 Txy, 10 Txz, 11 Tyy, 12 Tyz, 13 Tzz
+  return dim == 3 || (dim == 2 ? (k != 3 && k != 7 && k != 10 && k != 12 && k != 13)
+                               : (k == 0 || k == 1 || k == 4 || k == 5 || k == 8));
+}
+
 #define RLBM_LANDAU_NEWTON 0      // Newton on det(lambda I - T eta) from lambda = T^00
 #define RLBM_LANDAU_FIXED_POINT 1 // eps = T^00 - T^0i u_i, u_i = (T^0i - T^ij u_j)/eps
 
