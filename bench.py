@@ -428,17 +428,18 @@ def main():
     st = workloads.STENCILS["zeta1"]
     N = 2048
     kh = to_dev(workloads.kelvin_helmholtz(N, N, seed=0))
-    net, training = train_guess(st)
     W, K = args.warmup, args.steps
 
     if args.only:
         p = args.only
+        net = train_guess(st)[0] if "guess" in p else None
         rec, _ = run_path(st, kh, p.split("_")[0], K, W, tau=TAU_KH2048,
                           landau="fixed_point" if p.endswith("fixed_point") else "newton",
                           guess=net if "guess" in p else None, warm="warm" in p, keep=False)
         print(json.dumps({"path": p, **rec}))
         return
 
+    net, training = train_guess(st)
     head, o_head = run_path(st, kh, "fp32", K, W, tau=TAU_KH2048, landau="fixed_point", guess=net)
     paths = {}
     if not args.no_compare:
