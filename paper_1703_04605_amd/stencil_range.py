@@ -131,6 +131,38 @@ def stencil_map(lo=0.3, hi=40.0, points=36, max_norm2=18, processes=8):
             "smallest_per_point": best}
 
 
+def _probe3(args):
+    cand, mbar = args
+    from paper_1703_04605_amd import rlbm
+    try:
+        i = rlbm.solve_stencil(cand, mbar, 0.0, dim=3, order=3)
+        return cand, (i["q3"], i["v0"], i["v0_lo"], i["v0_hi"], min(i["weights"]), i["cond"])
+    except rlbm.RlbmError as e:
+        if e.code != rlbm.RLBM_ENOSTENCIL:
+            raise
+        return cand, None
+
+
+def search3(mbar, samples=4000, max_norm2=18, seed=0, processes=4):
+    """Third order (Sec. III.D: eleven groups): a seeded random sample of
+    eleven-group stencils {(0,0,0)} + ten groups with |n|^2 <= max_norm2,
+    probed at mbar with the library's solver (about 30 ms per candidate).
+    Returns the working ones as (base vectors, (populations, v0, v0_lo,
+    v0_hi, smallest weight, condition number)), fewest populations first."""
+    import random
+    from multiprocessing import get_context
+    rng = random.Random(seed)
+    pool = base_vectors(max_norm2)
+    cands = set()
+    while len(cands) < samples:
+        cands.add(tuple(sorted(rng.sample(range(len(pool)), 10))))
+    args = [([(0, 0, 0)] + [pool[i] for i in c], mbar) for c in sorted(cands)]
+    with get_context("spawn").Pool(processes) as p:
+        res = p.map(_probe3, args, chunksize=32)
+    ok = [(c, r) for c, r in res if r is not None]
+    return sorted(ok, key=lambda t: (t[1][0], -t[1][4]))
+
+
 def compact(m):
     """A compact form of ``stencil_map``'s result for storage: per grid point
     the number of working stencils, the smallest and the median condition
