@@ -272,13 +272,20 @@ int rlbm_moments3(rlbm_ctx* ctx, double* n, double* eps, double* T, double* P, d
  * (eq. mj-discrete-second-moment), Landau frame (eqs. landau-lifshitz-*),
  * EOS inversion (eq. relativistic-eos), projections (Appendix B), equilibrium
  * (eq. mj-discrete-feq), Anderson-Witting relaxation and exact streaming.
+ * Third-order stencils (order 3) take the equilibrium of eq.
+ * mj-projected-distribution at N = 3 instead (30 polynomials).
  * Asynchronous on stream; launch errors are returned at once (RLBM_EHIP).
- * Health flags accumulate on the device (rlbm_get_health).
+ * Health flags accumulate on the device: the call returns before any site
+ * is computed, so a fatal flag is reported by rlbm_get_health (RLBM_ENUMERIC)
+ * and not by this call; RLBM_ESTATE before rlbm_init_fields.
  */
 int rlbm_step(rlbm_ctx* ctx, int nsteps, void* stream);
 
 /*
- * Writes the macroscopic fields of the current (pre-collision) state f(x, t):
+ * Writes the macroscopic fields of the current state f(x, t), which is the
+ * pre-collision state: a step collides, then streams (eq.
+ * discrete-relativistic-boltzmann), and the fields are those of eqs.
+ * landau-lifshitz-* and relativistic-eos for the moments of f(x, t):
  * n, eps, T, P = nT, ux, uy (device float64, nx*ny each, any may be NULL) and
  * raw9 (device float64 [9][ny][nx] or NULL): N^0, N^x, N^y, T^00, T^0x,
  * T^0y, T^xx, T^xy, T^yy.
