@@ -137,9 +137,9 @@ def _probe3(args):
     try:
         i = rlbm.solve_stencil(cand, mbar, 0.0, dim=3, order=3)
         return cand, (i["q3"], i["v0"], i["v0_lo"], i["v0_hi"], min(i["weights"]), i["cond"])
-    except rlbm.RlbmError as e:
-        if e.code != rlbm.RLBM_ENOSTENCIL:
-            raise
+    except rlbm.RlbmError:
+        # no positive window (RLBM_ENOSTENCIL), or more populations than the
+        # library's tables hold (RLBM_EINVAL): not usable either way
         return cand, None
 
 
