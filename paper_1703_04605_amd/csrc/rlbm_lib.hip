@@ -892,10 +892,16 @@ k_step3(RlbmStepArgs a) {
 constexpr int kO3Chunk = 8;
 
 // D: the stencil's class dimension (1, 2: merged classes, only the moments
-// and equilibrium terms that can be nonzero; 3: every population)
-template <int D>
+// and equilibrium terms that can be nonzero; 3: every population).
+// P: float64 storage, or float32 deviations d = f - f^ref (sums in float32
+// over hi + lo rows, the reference's moments and projections added in
+// float64, as in the second-order float32 step).
+template <int D, int P>
 __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
   typedef const __attribute__((address_space(4))) unsigned* OffPtr;
+  using S = typename Traits<P>::S;
+  using A = typename Traits<P>::A;
+  constexpr bool kF32 = P == RLBM_FP32_DEV;
   const TabPtr tb = as_tab(a.tab);
   const RlbmLayout& L = a.L;
   const int lane = (int)threadIdx.x & (kWave - 1);
@@ -912,94 +918,131 @@ __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
   const long long lo =
       (long long)(z + L.GZ - L.Sz) * L.zs + (long long)(y + L.GY - L.Sy) * L.rs + L.GX - L.Sx + x0;
   const __amdgpu_buffer_rsrc_t rs_ld = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)((const char*)a.src + lo * (long long)sizeof(double)), (short)0, kRecAll, kRsrcWord3);
+      (void*)((const char*)a.src + lo * (long long)sizeof(S)), (short)0, kRecAll, kRsrcWord3);
   const __amdgpu_buffer_rsrc_t rs_st = __builtin_amdgcn_make_buffer_rsrc(
-      (void*)((char*)a.dst + lo * (long long)sizeof(double)), (short)0, kRecAll, kRsrcWord3);
-  const int vld = min(lane, nvalid - 1) * (int)sizeof(double);
-  const int vst = active ? lane * (int)sizeof(double) : kRecOut;
+      (void*)((char*)a.dst + lo * (long long)sizeof(S)), (short)0, kRecAll, kRsrcWord3);
+  const int vld = min(lane, nvalid - 1) * (int)sizeof(S);
+  const int vst = active ? lane * (int)sizeof(S) : kRecOut;
   const OffPtr pull = (OffPtr)a.offs;
   const OffPtr own = (OffPtr)a.offs_st;
+  auto pull_one = [&](int j) -> A {
+    if constexpr (kF32)
+      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs_ld, vld, pull[j], 0));
+    else
+      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs_ld, vld, pull[j], 0));
+  };
 
   // populations go in chunks of kO3Chunk: all pulls of a chunk are issued
   // before the first is used (a class-by-class loop would wait out one
   // memory round trip per class); the last chunk re-reads class Q - 1
-  double m[RLBM_NB3];
+  A m[RLBM_NB3], ml[RLBM_NB3];
 #pragma unroll
-  for (int k = 0; k < RLBM_NB3; ++k) m[k] = 0.0;
+  for (int k = 0; k < RLBM_NB3; ++k) m[k] = ml[k] = A(0);
   for (int j0 = 0; j0 < Q; j0 += kO3Chunk) {
-    double f[kO3Chunk];
+    A f[kO3Chunk];
 #pragma unroll
-    for (int i = 0; i < kO3Chunk; ++i)
-      f[i] = __builtin_bit_cast(double,
-                                __builtin_amdgcn_raw_buffer_load_b64(rs_ld, vld, pull[min(j0 + i, Q - 1)], 0));
+    for (int i = 0; i < kO3Chunk; ++i) f[i] = pull_one(min(j0 + i, Q - 1));
 #pragma unroll
     for (int i = 0; i < kO3Chunk; ++i) {
       const int j = min(j0 + i, Q - 1);
-      const double fi = j0 + i < Q ? f[i] : 0.0;
+      const A fi = j0 + i < Q ? f[i] : A(0);
 #pragma unroll
-      for (int k = 0; k < RLBM_NB3; ++k)
-        if (o3_mom_active(D, k)) m[k] = fma(fi, tb->rowm3d[j][k], m[k]);
+      for (int k = 0; k < RLBM_NB3; ++k) {
+        if (!o3_mom_active(D, k)) continue;
+        if constexpr (kF32) {
+          m[k] = fmaf(fi, tb->rowm3f[j][k], m[k]);
+          ml[k] = fmaf(fi, tb->rowm3f_lo[j][k], ml[k]);
+        } else {
+          m[k] = fma(fi, tb->rowm3d[j][k], m[k]);
+        }
+      }
       // (keeps the scalar row loads of later classes from piling up in SGPRs)
       __builtin_amdgcn_sched_barrier(0);
     }
   }
+  double md[RLBM_NB3];
+#pragma unroll
+  for (int k = 0; k < RLBM_NB3; ++k)
+    md[k] = kF32 ? tb->c.ref_mom3[k] + ((double)m[k] + (double)ml[k]) : (double)m[k];
 
   // Landau frame, density, EOS
   unsigned flags = 0;
   double eps, u[3];
-  const int iters = landau_newton3(m, newton_thresh(a.landau_tol), a.landau_maxit, eps, u, m[4]);
+  const int iters = landau_newton3(md, newton_thresh(a.landau_tol), a.landau_maxit, eps, u, md[4]);
   if (iters > a.landau_maxit) flags |= RLBM_H_LANDAU;
   const double u2 = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   if (!(u2 < 1.0)) flags |= RLBM_H_SUPERLUMINAL;
   const double gamma = rsqrt_nr(1.0 - u2);
-  const double n = gamma * (m[0] - u[0] * m[1] - u[1] * m[2] - u[2] * m[3]);
+  const double n = gamma * (md[0] - u[0] * md[1] - u[1] * md[2] - u[2] * md[3]);
   if (!(n > 0.0) || !(eps > 0.0)) flags |= RLBM_H_RANGE;
   const double T = eos_temperature_tab(tb, div_nr(eps, n), tb->c.zeta, flags);
   if (!isfinite(T) || !isfinite(eps) || !isfinite(n)) flags |= RLBM_H_NAN;
   const double tau = a.tau_mode == RLBM_TAU_CONST ? a.tau : tau_eta_over_s(a.tk1, a.tk2, n, T);
   const double U[4] = {gamma, gamma * u[0], gamma * u[1], gamma * u[2]};
-  double Mr[RLBM_NO3], M[RLBM_NO3];
+  double Mr[RLBM_NO3], Md[RLBM_NO3];
   mj_moments_o3(n, eps, n * T, T, tb->c.inv_zeta, tb->c.zeta, U, Mr);
-  centred_o3(Mr, tb->c.o3_c, tb->c.o3_is0, tb->c.o3_isp, M);
+  centred_o3(Mr, tb->c.o3_c, tb->c.o3_is0, tb->c.o3_isp, Md);
+  A M[RLBM_NO3];
+#pragma unroll
+  for (int k = 0; k < RLBM_NO3; ++k) M[k] = (A)(kF32 ? Md[k] - tb->c.o3_aref[k] : Md[k]);
   const double w0 = a.tau_mode == RLBM_TAU_CONST ? gamma * a.inv_tau : div_nr(gamma, tau);
   const double v0 = tb->c.v0;
-  const double WX = -w0 * v0 * u[0], WY = -w0 * v0 * u[1], WZ = -w0 * v0 * u[2];
+  const A W0 = (A)w0, WX = (A)(-w0 * v0 * u[0]), WY = (A)(-w0 * v0 * u[1]), WZ = (A)(-w0 * v0 * u[2]);
 
   const unsigned zm = (z < L.Sz || z >= L.nz - L.Sz) ? ghost_mask(z, L.nz, L.Sz, L.bc_z) : 0u;
   const unsigned ym = (y < L.Sy || y >= L.ny - L.Sy) ? ghost_mask(y, L.ny, L.Sy, L.bc_y) : 0u;
   const bool xedge = x0 < L.Sx || x0 + kWave > L.nx - L.Sx;
   const bool ghosts = xedge || ym != 0u || zm != 0u;
   const unsigned xm = xedge ? ghost_mask(x, L.nx, L.Sx, L.bc_x) : 0u;
-  double* __restrict__ dst = (double*)a.dst;
+  S* __restrict__ dst = (S*)a.dst;
   for (int j0 = 0; j0 < Q; j0 += kO3Chunk) {
-    double f[kO3Chunk];
+    A f[kO3Chunk];
 #pragma unroll
-    for (int i = 0; i < kO3Chunk; ++i)
-      f[i] = __builtin_bit_cast(double,
-                                __builtin_amdgcn_raw_buffer_load_b64(rs_ld, vld, pull[min(j0 + i, Q - 1)], 0));
+    for (int i = 0; i < kO3Chunk; ++i) f[i] = pull_one(min(j0 + i, Q - 1));
 #pragma unroll
     for (int i = 0; i < kO3Chunk; ++i) {
       const int j = j0 + i;
       if (j >= Q) break;
-      const auto& r = tb->rowo3[j];
       constexpr O3Act act = kO3Act[D];
-      double feq = M[act.m[0]] * r[0];
+      A diff, om;
+      if constexpr (kF32) {
+        const auto& r = tb->rowo3f[j];
+        const auto& rl = tb->rowo3f_lo[j];
+        float feq = M[act.m[0]] * r[0], feql = M[act.m[0]] * rl[0];
 #pragma unroll
-      for (int k = 1; k < act.n; ++k) feq = fma(M[act.m[k]], r[k], feq);
-      double om = fma(WX, r[RLBM_RO3_NX], w0);
-      if (D >= 2) om = fma(WY, r[RLBM_RO3_NY], om);
-      if (D == 3) om = fma(WZ, r[RLBM_RO3_NZ], om);
-      const double out = fma(-om, f[i] - feq, f[i]);
-      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, out), rs_st, vst, own[j], 0);
-      if (ghosts && active) store_ghosts3(dst + (long long)j * L.cs, L, x, y, z, xm, ym, zm, out);
+        for (int k = 1; k < act.n; ++k) {
+          feq = fmaf(M[act.m[k]], r[k], feq);
+          feql = fmaf(M[act.m[k]], rl[k], feql);
+        }
+        diff = (f[i] - feq) - feql;
+        om = fmaf(WX, r[RLBM_RO3_NX], W0);
+        if (D >= 2) om = fmaf(WY, r[RLBM_RO3_NY], om);
+        if (D == 3) om = fmaf(WZ, r[RLBM_RO3_NZ], om);
+      } else {
+        const auto& r = tb->rowo3[j];
+        double feq = M[act.m[0]] * r[0];
+#pragma unroll
+        for (int k = 1; k < act.n; ++k) feq = fma(M[act.m[k]], r[k], feq);
+        diff = f[i] - feq;
+        om = fma(WX, r[RLBM_RO3_NX], W0);
+        if (D >= 2) om = fma(WY, r[RLBM_RO3_NY], om);
+        if (D == 3) om = fma(WZ, r[RLBM_RO3_NZ], om);
+      }
+      const A out = fma(-om, diff, f[i]);
+      if constexpr (kF32)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, out), rs_st, vst, own[j], 0);
+      else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, out), rs_st, vst, own[j], 0);
+      if (ghosts && active) store_ghosts3(dst + (long long)j * L.cs, L, x, y, z, xm, ym, zm, (S)out);
       __builtin_amdgcn_sched_barrier(0);
     }
   }
   wave_stats(a.slots, t, active ? flags : 0u, active ? (unsigned)iters : 0u, active ? (unsigned)iters : 0u);
 }
 
-// f_i(x, 0) = f_i^eq(n, T, u) at third order (D as in k_step_o3)
-template <int D>
+// f_i(x, 0) = f_i^eq(n, T, u) at third order (D, P as in k_step_o3; float32
+// storage keeps f^eq - f^ref = R . (a - a^ref))
+template <int D, int P>
 __global__ void __launch_bounds__(kBlock) k_init_o3(RlbmInitArgs a, const double* __restrict__ uz) {
   const TabPtr tb = as_tab(a.tab);
   const RlbmLayout& L = a.L;
@@ -1016,14 +1059,18 @@ __global__ void __launch_bounds__(kBlock) k_init_o3(RlbmInitArgs a, const double
   double Mr[RLBM_NO3], M[RLBM_NO3];
   mj_moments_o3(n, eps, n * T, T, tb->c.inv_zeta, tb->c.zeta, U, Mr);
   centred_o3(Mr, tb->c.o3_c, tb->c.o3_is0, tb->c.o3_isp, M);
-  double* __restrict__ dst = (double*)a.dst;
   const long long o = (long long)(z + L.GZ) * L.zs + (long long)(y + L.GY) * L.rs + x + L.GX;
   constexpr O3Act act = kO3Act[D];
+  if (P == RLBM_FP32_DEV)
+    for (int k = 0; k < RLBM_NO3; ++k) M[k] -= tb->c.o3_aref[k];
   for (int j = 0; j < tb->c.Q; ++j) {
     double fe = 0.0;
 #pragma unroll
     for (int k = 0; k < act.n; ++k) fe = fma(M[act.m[k]], tb->rowo3[j][k], fe);
-    dst[(long long)j * L.cs + o] = fe;
+    if (P == RLBM_FP32_DEV)
+      ((float*)a.dst)[(long long)j * L.cs + o] = (float)fe;
+    else
+      ((double*)a.dst)[(long long)j * L.cs + o] = fe;
   }
 }
 
@@ -1630,12 +1677,13 @@ static int init_fields_impl(rlbm_ctx* c, const rlbm_lattice_desc* lat, const dou
   long long sites = (long long)lat->nx * lat->ny * nz;
   dim3 grid((unsigned)((sites + kBlock - 1) / kBlock));
   if (k.order == 3) {
-    if (k.dim == 1)
-      hipLaunchKernelGGL(k_init_o3<1>, grid, dim3(kBlock), 0, s, ia, uz);
-    else if (k.dim == 2)
-      hipLaunchKernelGGL(k_init_o3<2>, grid, dim3(kBlock), 0, s, ia, uz);
+    typedef void (*InitO3)(RlbmInitArgs, const double*);
+    InitO3 ik;
+    if (k.precision == RLBM_FP32_DEV)
+      ik = k.dim == 1 ? k_init_o3<1, RLBM_FP32_DEV> : k.dim == 2 ? k_init_o3<2, RLBM_FP32_DEV> : k_init_o3<3, RLBM_FP32_DEV>;
     else
-      hipLaunchKernelGGL(k_init_o3<3>, grid, dim3(kBlock), 0, s, ia, uz);
+      ik = k.dim == 1 ? k_init_o3<1, RLBM_FP64> : k.dim == 2 ? k_init_o3<2, RLBM_FP64> : k_init_o3<3, RLBM_FP64>;
+    hipLaunchKernelGGL(ik, grid, dim3(kBlock), 0, s, ia, uz);
   } else if (three_d) {
     switch (k.precision) {
       case RLBM_FP64: hipLaunchKernelGGL(k_init3<RLBM_FP64>, grid, dim3(kBlock), 0, s, ia, uz); break;
@@ -1698,8 +1746,13 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   }
   const bool d3 = layout3(c->h_tab->c);
   StepFn fn = (!d3 && c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? fixed_step(c->fixed_id, g) : nullptr;
-  if (!fn && c->h_tab->c.order == 3)
-    fn = c->h_tab->c.dim == 1 ? k_step_o3<1> : c->h_tab->c.dim == 2 ? k_step_o3<2> : k_step_o3<3>;
+  if (!fn && c->h_tab->c.order == 3) {
+    const int dim = c->h_tab->c.dim;
+    if (c->h_tab->c.precision == RLBM_FP32_DEV)
+      fn = dim == 1 ? k_step_o3<1, RLBM_FP32_DEV> : dim == 2 ? k_step_o3<2, RLBM_FP32_DEV> : k_step_o3<3, RLBM_FP32_DEV>;
+    else
+      fn = dim == 1 ? k_step_o3<1, RLBM_FP64> : dim == 2 ? k_step_o3<2, RLBM_FP64> : k_step_o3<3, RLBM_FP64>;
+  }
   if (!fn) fn = d3 ? select_step3(c->h_tab->c.precision, c->h_tab->c.Q) : select_step(c->h_tab->c.precision, c->h_tab->c.Q, g);
   if (!fn) return fail(c, RLBM_ESTATE, "no step kernel for this stencil");
   a.tiles_x = c->tiles_x;

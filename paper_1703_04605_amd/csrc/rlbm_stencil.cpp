@@ -521,8 +521,8 @@ static ld k1k2_ld(ld z) { return besselk_scaled_ld(1, z) / besselk_scaled_ld(2, 
 // the raw moment tensors) and R_i = w_i L^-T J(p_i).
 static int build_table_o3(const rlbm_stencil_desc* d, rlbm_stencil_info* info, RlbmTable* tab, char* err,
                           size_t errlen) {
-  if (d->n_groups != 11 || d->precision != RLBM_FP64) {
-    set_err(err, errlen, "third order needs 11 groups and float64 storage");
+  if (d->n_groups != 11 || (d->precision != RLBM_FP64 && d->precision != RLBM_FP32_DEV)) {
+    set_err(err, errlen, "third order needs 11 groups and float64 or float32-deviation storage");
     return RLBM_EINVAL;
   }
   Stencil3 st((ld)d->zeta, d->n_groups, d->group_base);
@@ -772,6 +772,54 @@ static int build_table_o3(const rlbm_stencil_desc* d, rlbm_stencil_info* info, R
     const ld mono[RLBM_NB3] = {e,      px,      py,      pz,      e * e,   e * px, e * py,
                                e * pz, px * px, px * py, px * pz, pyy,     py * pz, pzz};
     for (int a = 0; a < RLBM_NB3; ++a) tab->rowm3d[j][a] = (double)mono[a];
+  }
+  if (d->precision == RLBM_FP32_DEV) {
+    // deviation reference f^ref = f^eq(n_ref, T_ref, u = 0): raw moments of
+    // the Maxwell-Juttner distribution at rest (rank <= 3), their centred
+    // combinations a^ref, f^ref_j = R_j . a^ref and the moments of f^ref
+    const ld nref = d->n_ref > 0 ? d->n_ref : 1.0L, Tref = d->T_ref > 0 ? d->T_ref : 1.0L;
+    c.n_ref = (double)nref;
+    c.T_ref = (double)Tref;
+    const ld e = nref * (3.0L * Tref + m * k1k2_ld(m / Tref)), P = nref * Tref, h = e + P;
+    const ld a3 = nref * m * m + 6.0L * Tref * h, b3 = -Tref * h;
+    const ld U[4] = {1.0L, 0.0L, 0.0L, 0.0L};
+    auto eta = [](int a, int b) { return a != b ? 0.0L : (a == 0 ? 1.0L : -1.0L); };
+    ld Mr[RLBM_NO3];
+    for (int i = 0; i < RLBM_NO3; ++i) {
+      const int a = kO3Idx[i][0], b = kO3Idx[i][1], cc = kO3Idx[i][2];
+      if (a < 0)
+        Mr[i] = (e - 3.0L * P) / (m * m);
+      else if (b < 0)
+        Mr[i] = nref * U[a];
+      else if (cc < 0)
+        Mr[i] = h * U[a] * U[b] - P * eta(a, b);
+      else
+        Mr[i] = a3 * U[a] * U[b] * U[cc] + b3 * (eta(a, b) * U[cc] + eta(a, cc) * U[b] + eta(b, cc) * U[a]);
+    }
+    ld aref[RLBM_NO3];
+    for (int a = 0; a < RLBM_NO3; ++a) {
+      ld sum = 0;
+      for (int r = 0; r < RLBM_NO3; ++r) sum += B[a * RLBM_NO3 + r] * Mr[r];
+      aref[a] = sum;
+      c.o3_aref[a] = (double)sum;
+    }
+    const O3Act& act = kO3Act[d->dim];
+    ld refm[RLBM_NB3] = {};
+    for (int j = 0; j < Q; ++j) {
+      ld fr = 0;
+      for (int r = 0; r < act.n; ++r) fr += (ld)tab->rowo3[j][r] * aref[(int)act.m[r]];
+      for (int a = 0; a < RLBM_NB3; ++a) {
+        const ld mono = (ld)tab->rowm3d[j][a];
+        refm[a] += fr * mono;
+        tab->rowm3f[j][a] = (float)mono;
+        tab->rowm3f_lo[j][a] = (float)(mono - (ld)tab->rowm3f[j][a]);
+      }
+      for (int r = 0; r < RLBM_ROWO3; ++r) {
+        tab->rowo3f[j][r] = (float)tab->rowo3[j][r];
+        tab->rowo3f_lo[j][r] = (float)((ld)tab->rowo3[j][r] - (ld)tab->rowo3f[j][r]);
+      }
+    }
+    for (int a = 0; a < RLBM_NB3; ++a) c.ref_mom3[a] = (double)refm[a];
   }
   return RLBM_OK;
 }

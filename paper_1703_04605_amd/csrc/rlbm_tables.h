@@ -143,6 +143,7 @@ struct RlbmConsts {
   double nb_ref3[RLBM_NB3];  // 3D: n_ref * b_k(rest, T_ref) for all 14 polynomials
   double ref_mom3[RLBM_NB3]; // 3D: sum_j f^ref_j times the 14 monomials of the 3D moment rows
   double o3_c, o3_is0, o3_isp;  // third order: centre c of p0, 1/s0, 1/sp of the q basis
+  double o3_aref[RLBM_NO3];     // third order, float32 storage: projections a_m of f^ref
 };
 
 struct RlbmTable {
@@ -191,6 +192,10 @@ struct RlbmTable {
   // third-order equilibrium rows (layout above; classes of dim 1 and 2 carry
   // the sums over their members and n_z = 0)
   double rowo3[RLBM_QMAX][RLBM_ROWO3] __attribute__((aligned(64)));
+  // float32 storage: the same rows rounded to float, and their rounding
+  // remainders (hi + lo carries each coefficient to about 2^-48)
+  float rowo3f[RLBM_QMAX][RLBM_ROWO3] __attribute__((aligned(64)));
+  float rowo3f_lo[RLBM_QMAX][RLBM_ROWO3] __attribute__((aligned(64)));
 };
 
 // Per-block health / statistics slot, accumulated by the step kernel.
