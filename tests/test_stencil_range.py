@@ -116,9 +116,10 @@ def test_condition_number_matches_oracle_system(name):
     assert abs(info["cond"] - cond) < 1e-9 * cond, (info["cond"], cond)
 
 
-def test_stored_map_against_oracle():
-    """Sampled entries of the stored working-range map (all six-group
-    stencils with |n|^2 <= 18, written by stencil_range.stencil_map): where
+@pytest.mark.parametrize("n2", [18, 29])
+def test_stored_map_against_oracle(n2):
+    """Sampled entries of the stored working-range maps (all six-group
+    stencils with |n|^2 <= 18 and <= 29, written by stencil_range.stencil_map): where
     the map says a stencil works, the oracle's weights at the library's v0
     are all positive; at the grid point just below the smallest working mass
     the oracle's own window search finds no positive window for the stencil
@@ -127,8 +128,9 @@ def test_stored_map_against_oracle():
     import os
     import random
     from paper_1703_04605_amd import rlbm
-    path = os.path.join(os.path.dirname(sr.__file__), "stencil_map_n18.json")
+    path = os.path.join(os.path.dirname(sr.__file__), f"stencil_map_n{n2}.json")
     m = json.load(open(path))
+    assert m["max_norm2"] == n2
     grid = m["grid"]
     vec = lambda s: tuple(int(c) for c in s)
     rng = random.Random(5)
