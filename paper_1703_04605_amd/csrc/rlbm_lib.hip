@@ -2040,6 +2040,8 @@ constexpr int kSyncAbort = 2 * kBatchXcds;     // set when a wave gives up
 constexpr int kSyncDone = 2 * kBatchXcds + 1;  // [ntiles] steps completed per tile
 constexpr unsigned kSpinLimit = 1u << 20;      // ~100 ms of polling per wait
 
+struct BatchRow;
+
 struct RlbmBatchArgs {
   const void* src;
   void* dst;
@@ -2052,6 +2054,7 @@ struct RlbmBatchArgs {
   const RlbmBatchTile* tiles;
   int ntiles;
   const RlbmTable* const* tables;
+  const BatchRow* rows;  // [stencil][kBatchQ] packed 1D rows
   double landau_tol;
   int landau_maxit;
   RlbmSlot* slots;      // one per wave of the grid
@@ -2060,32 +2063,64 @@ struct RlbmBatchArgs {
   int xoff[kBatchXcds + 1];
 };
 
-// One site of one problem: pull, moments (float32 rows plus their rounding
-// remainders), Landau frame, EOS, projections, equilibrium and relaxation,
-// store (and the outflow ghosts at the ends).
-__device__ __forceinline__ void batch_site(const RlbmBatchArgs& a, const RlbmBatchProblem& pr, TabPtr tb,
-                                           const float* __restrict__ src, float* __restrict__ dst, int x, int shift,
-                                           float* __restrict__ sample, unsigned& flags, unsigned& iters) {
-  const int Q = tb->c.Q;
+// Per-class coefficients of the 1D stencils, packed per stencil into one
+// compact block (built on the host at batch creation) and read through scalar
+// loads: a CU's waves step problems with different stencils, and the packed
+// rows of several stencils fit the scalar cache together where the full
+// tables do not.  A 1D class has p^y = 0, so the moment monomials odd in p^y
+// or containing p^y p^y vanish (N^y, T^0y, T^xy, T^yy), u_y = 0, and the
+// projections b_3, b_6, b_7, b_9 (odd in U_y or proportional to U_y^2)
+// vanish with their reference values: only the terms below can be nonzero,
+// so dropping the others changes no result.
+constexpr int kBMom[5] = {0, 1, 3, 4, 6};      // N^0, N^x, T^00, T^0x, T^xx
+constexpr int kBEq[6] = {0, 1, 2, 4, 5, 8};    // b_0, b_1, b_2, b_4, b_5, b_8
+// 24 floats per class: moment rows (5) and n_x as float; their remainders (5)
+// and n_x as int bits; equilibrium rows (6); their remainders (6)
+constexpr int kBRow = 24;
+struct alignas(16) BatchRow {
+  float v[kBRow];
+};
+typedef const __attribute__((address_space(4))) BatchRow* BatchRowPtr;
+
+// One site per lane of a 64-site tile of one problem: pull, moments (float32
+// rows plus their rounding remainders), Landau frame, EOS, projections,
+// equilibrium and relaxation, store, and the outflow ghosts at the problem's
+// ends.  All lanes run: a lane past the end (act false) repeats the last site
+// without storing, so the ghosts are written by one masked vector store per
+// class (lanes 0..S-1) from the end site's value.
+__device__ __forceinline__ void batch_site(const RlbmBatchArgs& a, const RlbmBatchProblem& pr, TabPtr tb, int Q,
+                                           BatchRowPtr R, const float* __restrict__ src, float* __restrict__ dst,
+                                           int x, int x0,
+                                           bool act, int shift, float* __restrict__ sample, unsigned& flags,
+                                           unsigned& iters) {
+  const int lane = (int)threadIdx.x & (kWave - 1);
+  const bool first = x0 == 0;                  // the tile holds site 0
+  const bool last = x0 + kWave >= pr.L;        // the tile holds site L - 1
+  const int lend = min(pr.L - 1 - x0, kWave - 1);
   float f[kBatchQ];
 #pragma unroll
-  for (int j = 0; j < kBatchQ; ++j)
-    f[j] = j < Q ? src[pr.base + (long long)j * pr.W + x + pr.S - (shift ? tb->nx[j] : 0)] : 0.0f;
-  float m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  float ml[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int j = 0; j < kBatchQ; ++j) {
+    const int nxj = j < Q ? __float_as_int(R[j].v[11]) : 0;
+    f[j] = j < Q ? src[pr.base + (long long)j * pr.W + x + pr.S - (shift ? nxj : 0)] : 0.0f;
+  }
+  float m[5] = {0, 0, 0, 0, 0};
+  float ml[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int j = 0; j < kBatchQ; ++j) {
     if (j < Q) {
+      const BatchRow r = load_row(R + j);
 #pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        m[k] = fmaf(f[j], tb->rowmf[j][k], m[k]);
-        ml[k] = fmaf(f[j], tb->rowmf_lo[j][k], ml[k]);
+      for (int k = 0; k < 5; ++k) {
+        m[k] = fmaf(f[j], r.v[k], m[k]);
+        ml[k] = fmaf(f[j], r.v[6 + k], ml[k]);
       }
     }
   }
   double md[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) md[k] = tb->c.ref_mom[k] + ((double)m[k] + (double)ml[k]);
+  for (int k = 0; k < 9; ++k) md[k] = tb->c.ref_mom[k];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) md[kBMom[k]] += (double)m[k] + (double)ml[k];
   Macro mac = macroscopic(tb, md[0], md[1], md[2], md[3], md[4], md[5], md[6], md[7], md[8], a.landau_tol,
                           a.landau_maxit, RLBM_LANDAU_NEWTON);
   flags |= mac.flags;
@@ -2101,30 +2136,35 @@ __device__ __forceinline__ void batch_site(const RlbmBatchArgs& a, const RlbmBat
   double b[RLBM_NB];
   projections(tb, mac.T, mac.R, mac.gamma, mac.gamma * mac.ux, mac.gamma * mac.uy, b);
   const double w0 = div_nr(mac.gamma, tau);
-  const float W0 = (float)w0, WX = (float)(-w0 * tb->c.v0 * mac.ux), WY = (float)(-w0 * tb->c.v0 * mac.uy);
-  float nb[RLBM_NB];
+  const float W0 = (float)w0, WX = (float)(-w0 * tb->c.v0 * mac.ux);
+  float nb[6];
 #pragma unroll
-  for (int k = 0; k < RLBM_NB; ++k) nb[k] = (float)(mac.n * b[k] - tb->c.nb_ref[k]);
+  for (int k = 0; k < 6; ++k) nb[k] = (float)(mac.n * b[kBEq[k]] - tb->c.nb_ref[kBEq[k]]);
 #pragma unroll
   for (int j = 0; j < kBatchQ; ++j) {
     if (j < Q) {
-      const auto* r = tb->rowf[j];
-      const auto* rl = tb->rowf_lo[j];
-      float feq = nb[0] * r[0], feql = nb[0] * rl[0];
+      const BatchRow r = load_row(R + j);
+      const float* e = r.v + 12;
+      const float* el = r.v + 18;
+      float feq = nb[0] * e[0], feql = nb[0] * el[0];
 #pragma unroll
-      for (int k = 1; k < RLBM_NB; ++k) {
-        feq = fmaf(nb[k], r[k], feq);
-        feql = fmaf(nb[k], rl[k], feql);
+      for (int k = 1; k < 6; ++k) {
+        feq = fmaf(nb[k], e[k], feq);
+        feql = fmaf(nb[k], el[k], feql);
       }
-      const float om = fmaf(WY, r[RLBM_R_NY], fmaf(WX, r[RLBM_R_NX], W0));
+      const float om = fmaf(WX, r.v[5], W0);
       const float out = fmaf(-om, (f[j] - feq) - feql, f[j]);
       float* q = dst + pr.base + (long long)j * pr.W + pr.S;
-      q[x] = out;
+      if (act) q[x] = out;
       // outflow ghosts: the end sites stand for every site beyond them
-      if (x == 0)
-        for (int g = 1; g <= pr.S; ++g) q[-g] = out;
-      if (x == pr.L - 1)
-        for (int g = 1; g <= pr.S; ++g) q[pr.L - 1 + g] = out;
+      if (first) {
+        const float v = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, out), 0));
+        if (lane < pr.S) q[-1 - lane] = v;
+      }
+      if (last) {
+        const float v = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, out), lend));
+        if (lane < pr.S) q[pr.L + lane] = v;
+      }
     }
   }
 }
@@ -2165,7 +2205,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(RlbmBatchArgs a) {
     slot = (int)__hip_atomic_fetch_add(sync + kSyncCount + bin, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_fetch_or(sync + kSyncMask + bin, 1u << (xcc & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  slot = __shfl(slot, 0);
+  slot = __builtin_amdgcn_readfirstlane(__shfl(slot, 0));
   __threadfence();
   grid.sync();
   __threadfence();
@@ -2201,14 +2241,22 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch(RlbmBatchArgs a) {
       const int prob = __builtin_amdgcn_readfirstlane(tl.prob);
       const RlbmBatchProblem pr = a.probs[prob];
       const TabPtr tb = as_tab(a.tables[pr.table]);
-      const int x = __builtin_amdgcn_readfirstlane(tl.x0) + lane;
-      if (x < pr.L) {
-        float* srow = sampling ? a.samples + ((long long)(t / a.sample_every) * a.total_sites + pr.site_off + x) * 12
-                               : nullptr;
-        unsigned it = 0;
-        batch_site(a, pr, tb, src, dst, x, shift, srow, flags, it);
-        imax = max(imax, it);
-        isum += it;
+      const int Q = tb->c.Q;
+      const int x0 = __builtin_amdgcn_readfirstlane(tl.x0);
+      const int x = x0 + lane;
+      const bool act = x < pr.L;
+      {
+        float* srow = sampling && act
+                          ? a.samples + ((long long)(t / a.sample_every) * a.total_sites + pr.site_off + x) * 12
+                          : nullptr;
+        unsigned it = 0, fl = 0;
+        batch_site(a, pr, tb, Q, (BatchRowPtr)(a.rows + (long long)pr.table * kBatchQ), src, dst,
+                   act ? x : pr.L - 1, x0, act, shift, srow, fl, it);
+        if (act) {
+          flags |= fl;
+          imax = max(imax, it);
+          isum += it;
+        }
       }
       // this wave's stores have reached the XCD's L2 before the tile is
       // marked done (the L1 writes through)
@@ -2282,6 +2330,7 @@ struct rlbm_batch {
   std::vector<RlbmBatchProblem> h_probs;
   RlbmBatchProblem* d_probs = nullptr;
   const RlbmTable** d_tables = nullptr;
+  BatchRow* d_rows = nullptr;        // [stencil][kBatchQ] packed 1D rows
   long long total_sites = 0, total_elems = 0;
   void* buf[2] = {nullptr, nullptr};
   int cur = 0, shifted = 0;
@@ -2402,8 +2451,28 @@ extern "C" int rlbm_batch_create(rlbm_batch** out, int nstencils, rlbm_ctx* cons
   const int nwaves = b->workgroups * (kBatchBlock / kWave);
   std::vector<const RlbmTable*> tabs(nstencils);
   for (int s = 0; s < nstencils; ++s) tabs[s] = stencils[s]->d_tab;
+  // packed 1D rows of every stencil (layout of BatchRow)
+  std::vector<BatchRow> rows((size_t)nstencils * kBatchQ);
+  for (int s = 0; s < nstencils; ++s) {
+    const RlbmTable& t = *stencils[s]->h_tab;
+    for (int j = 0; j < t.c.Q; ++j) {
+      float* r = rows[(size_t)s * kBatchQ + j].v;
+      for (int k = 0; k < 5; ++k) {
+        r[k] = t.rowmf[j][kBMom[k]];
+        r[6 + k] = t.rowmf_lo[j][kBMom[k]];
+      }
+      r[5] = t.rowf[j][RLBM_R_NX];
+      int nx = t.nx[j];
+      memcpy(&r[11], &nx, sizeof(nx));
+      for (int k = 0; k < 6; ++k) {
+        r[12 + k] = t.rowf[j][kBEq[k]];
+        r[18 + k] = t.rowf_lo[j][kBEq[k]];
+      }
+    }
+  }
   if (hipMalloc((void**)&b->d_probs, sizeof(RlbmBatchProblem) * nprob) != hipSuccess ||
       hipMalloc((void**)&b->d_tables, sizeof(RlbmTable*) * nstencils) != hipSuccess ||
+      hipMalloc((void**)&b->d_rows, sizeof(BatchRow) * rows.size()) != hipSuccess ||
       hipMalloc((void**)&b->d_slots, sizeof(RlbmSlot) * nwaves) != hipSuccess ||
       hipMalloc((void**)&b->d_tiles, sizeof(RlbmBatchTile) * b->ntiles) != hipSuccess ||
       hipMalloc((void**)&b->d_xtiles, sizeof(int) * b->ntiles) != hipSuccess ||
@@ -2413,6 +2482,7 @@ extern "C" int rlbm_batch_create(rlbm_batch** out, int nstencils, rlbm_ctx* cons
   }
   BHIP(hipMemcpy(b->d_probs, b->h_probs.data(), sizeof(RlbmBatchProblem) * nprob, hipMemcpyHostToDevice));
   BHIP(hipMemcpy(b->d_tables, tabs.data(), sizeof(RlbmTable*) * nstencils, hipMemcpyHostToDevice));
+  BHIP(hipMemcpy(b->d_rows, rows.data(), sizeof(BatchRow) * rows.size(), hipMemcpyHostToDevice));
   BHIP(hipMemcpy(b->d_tiles, tiles.data(), sizeof(RlbmBatchTile) * b->ntiles, hipMemcpyHostToDevice));
   BHIP(hipMemcpy(b->d_xtiles, xtiles.data(), sizeof(int) * b->ntiles, hipMemcpyHostToDevice));
   BHIP(hipMemset(b->d_slots, 0, sizeof(RlbmSlot) * nwaves));
@@ -2433,6 +2503,7 @@ extern "C" int rlbm_batch_destroy(rlbm_batch* b) {
   (void)hipDeviceSynchronize();
   if (b->d_probs) (void)hipFree(b->d_probs);
   if (b->d_tables) (void)hipFree((void*)b->d_tables);
+  if (b->d_rows) (void)hipFree(b->d_rows);
   if (b->d_slots) (void)hipFree(b->d_slots);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->d_xtiles) (void)hipFree(b->d_xtiles);
@@ -2479,6 +2550,7 @@ extern "C" int rlbm_batch_step_persistent(rlbm_batch* b, int nsteps, int sample_
   a.total_sites = b->total_sites;
   a.probs = b->d_probs;
   a.tables = b->d_tables;
+  a.rows = b->d_rows;
   a.landau_tol = b->landau_tol;
   a.landau_maxit = b->landau_maxit;
   a.slots = b->d_slots;
