@@ -108,7 +108,9 @@ typedef struct {
                             mj-projected-distribution): 0 or 2 = second order
                             (14 polynomials, 6 groups); 3 = third order (30
                             polynomials, 11 groups, Sec. III.A and III.D),
-                            RLBM_FP64 only; third-order contexts of every dim
+                            RLBM_FP64 or RLBM_FP32_DEV (float32 deviations
+                            from f^eq(n_ref, T_ref, u=0)); RLBM_FP16_DEV is
+                            rejected (RLBM_EINVAL); third-order contexts of every dim
                             take rlbm_init_fields3 / rlbm_moments3 (nz = 1 for
                             dim 1 and 2, ny = 1 for dim 1) */
   const double* weights; /* host, nullable: n_groups weights (per population
