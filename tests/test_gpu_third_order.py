@@ -136,6 +136,29 @@ def test_third_order_1d_shock_tube_vs_oracle(setup):
     assert max(e.values()) < 1e-12, e
 
 
+def test_third_order_1d_fp32_vs_oracle(setup):
+    """dim 1 in float32 deviations: the pressure step of the shock tube above,
+    40 steps, against the oracle's 1D projected model, <= 1e-5."""
+    from oracle import lattice as L
+    bases, w = setup
+    nx = 150
+    x = np.arange(nx)
+    n = np.where(x < nx // 2, 1.0, 0.6)[None, None, :]
+    T = np.where(x < nx // 2, 1.0, 0.8)[None, None, :]
+    z = np.zeros_like(n)
+    g, h, info = gpu(bases, w, (n, T, z, z, z), 40, 1, ("outflow", "periodic", "periodic"), tau=0.8,
+                     precision="fp32")
+    assert info["q"] == 36 and h["flags"] == 0, (info, h)
+    ps = L.build_stencil(bases, MBAR, V0, mode="projected", dim=1, order=3, weights=w)
+    m = L.Model(ps, nx, 1, bc=("outflow", "periodic"), tau=0.8)
+    m.init_equilibrium(n[0], T[0], z[0], z[0])
+    m.step(40)
+    r = m.fields()
+    e = errs({k: g[k][0] for k in ("n", "eps", "T", "P", "ux")}, r, ("n", "eps", "T", "P", "ux"))
+    print(e)
+    assert max(e.values()) < 1e-5, e
+
+
 def test_third_order_conservation_and_fixed_point(setup):
     from tests.helpers import to_dev
     from paper_1703_04605_amd import rlbm
