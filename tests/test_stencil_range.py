@@ -148,3 +148,17 @@ def test_stored_map_against_oracle(n2):
     vmax = 1.0 / max(sum(c * c for c in b) for b in bases) ** 0.5
     assert quad.positive_window(bases, grid[first - 1], 0.02, vmax * (1 - 1e-9), grid=60, zoom=10, dps=30) is None
     assert not sr.works(bases, grid[first - 1])
+
+
+def test_third_order_search_against_oracle():
+    """The eleven-group search (seeded sample at mbar = 7.5): every stencil it
+    reports has all oracle weights positive at the library's v0, with the
+    465 pair conditions of eq. ortho2 met (checked for the two with the
+    fewest populations), and each lies inside its reported window."""
+    from oracle import third_order as t3
+    res = sr.search3(7.5, samples=1000, seed=3, processes=2)
+    assert len(res) >= 2, len(res)
+    for bases, (q3, v0, lo, hi, wmin, cond) in res[:2]:
+        assert lo < v0 < hi and wmin > 0 and cond > 1
+        w, r = t3.weights([tuple(b) for b in bases], 7.5, v0, dps=30)
+        assert min(w) > 0 and float(r) < 1e-20, (bases, v0)
