@@ -32,6 +32,10 @@
 // float coefficient alone would bias every step by its rounding (about 2^-25
 // relative), and that bias accumulates in the conserved quantities.
 //
+// 3D stencils (every population a class of its own) are factored the same
+// way over sign orbits: the populations whose displacements differ only in
+// the signs of their nonzero components (1, 2, 4 or 8 members, see orbits3).
+//
 // The output also carries each stencil's table fingerprint; the library uses
 // a generated kernel only for a context whose table has the same fingerprint.
 #include <math.h>
@@ -266,16 +270,9 @@ struct OrbitPlan {
 // Rows of the class loops: for float32 storage the float rows plus their
 // rounding remainders (the row values to about 2^-48), otherwise the float
 // rows as they are.
-static OrbitPlan plan_orbit(const RlbmTable& t, const std::vector<int>& o) {
+static OrbitPlan plan_rows(const std::vector<int>& o, const std::vector<std::vector<ld>>& Rm,
+                           const std::vector<std::vector<ld>>& Re) {
   const int n = (int)o.size();
-  std::vector<std::vector<ld>> Rm, Re;
-  for (int j : o) {
-    std::vector<ld> rm(9), re(RLBM_NB);
-    for (int k = 0; k < 9; ++k) rm[k] = (ld)t.rowmf[j][k] + (ld)t.rowmf_lo[j][k];
-    for (int k = 0; k < RLBM_NB; ++k) re[k] = (ld)t.rowf[j][k] + (ld)t.rowf_lo[j][k];
-    Rm.push_back(rm);
-    Re.push_back(re);
-  }
   OrbitPlan pl;
   pl.members = o;
   int best_m = 1 << 30, best_e = 1 << 30;
@@ -301,6 +298,18 @@ static OrbitPlan plan_orbit(const RlbmTable& t, const std::vector<int>& o) {
     }
   }
   return pl;
+}
+
+static OrbitPlan plan_orbit(const RlbmTable& t, const std::vector<int>& o) {
+  std::vector<std::vector<ld>> Rm, Re;
+  for (int j : o) {
+    std::vector<ld> rm(9), re(RLBM_NB);
+    for (int k = 0; k < 9; ++k) rm[k] = (ld)t.rowmf[j][k] + (ld)t.rowmf_lo[j][k];
+    for (int k = 0; k < RLBM_NB; ++k) re[k] = (ld)t.rowf[j][k] + (ld)t.rowf_lo[j][k];
+    Rm.push_back(rm);
+    Re.push_back(re);
+  }
+  return plan_rows(o, Rm, Re);
 }
 
 static std::string gen_struct(const char* sname, const RlbmTable& t) {
@@ -422,6 +431,149 @@ static std::string gen_struct(const char* sname, const RlbmTable& t) {
   return s;
 }
 
+// 3D stencils: every population is a class of its own.  Populations that
+// differ only in the signs of their displacement components form sign orbits
+// of 1, 2, 4 or 8 members (one energy p^0), taken in the order of the sign
+// bits of their nonzero components (x first), so that the butterflies of the
+// Walsh-Hadamard stages pair members that differ in one sign.
+static std::vector<std::vector<int>> orbits3(const RlbmTable& t) {
+  const int Q = t.c.Q;
+  std::map<std::tuple<double, int, int, int>, std::vector<int>> by;
+  for (int j = 0; j < Q; ++j)
+    by[std::make_tuple(t.p0[j], abs(t.nx[j]), abs(t.ny[j]), abs(t.nz[j]))].push_back(j);
+  std::vector<std::vector<int>> res;
+  for (auto& kv : by) {
+    const int a[3] = {std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first)};
+    int axes[3], k = 0;
+    for (int d = 0; d < 3; ++d)
+      if (a[d]) axes[k++] = d;
+    std::vector<int> m;
+    for (int sbits = 0; sbits < (1 << k); ++sbits) {
+      int want[3] = {a[0], a[1], a[2]};
+      for (int i = 0; i < k; ++i)
+        if (sbits >> i & 1) want[axes[i]] = -want[axes[i]];
+      for (int j : kv.second)
+        if (t.nx[j] == want[0] && t.ny[j] == want[1] && t.nz[j] == want[2]) m.push_back(j);
+    }
+    if ((int)m.size() == (1 << k) && m.size() == kv.second.size()) {
+      res.push_back(m);
+    } else {
+      for (int j : kv.second) res.push_back({j});  // not a full sign orbit: one by one
+    }
+  }
+  return res;
+}
+
+static std::string gen_struct3(const char* sname, const RlbmTable& t) {
+  const int Q = t.c.Q;
+  const bool split = t.c.precision == RLBM_FP32_DEV;
+  std::vector<OrbitPlan> plans;
+  for (auto& o : orbits3(t)) {
+    std::vector<std::vector<ld>> Rm, Re;
+    for (int j : o) {
+      std::vector<ld> rm(RLBM_NB3), re(RLBM_NB3);
+      for (int k = 0; k < RLBM_NB3; ++k) rm[k] = (ld)t.rowm3f[j][k] + (ld)t.rowm3f_lo[j][k];
+      for (int k = 0; k < RLBM_NB3; ++k) re[k] = (ld)t.row3f[j][k] + (ld)t.row3f_lo[j][k];
+      Rm.push_back(rm);
+      Re.push_back(re);
+    }
+    plans.push_back(plan_rows(o, Rm, Re));
+  }
+  Emitter em;
+  std::string s;
+  s += "struct " + std::string(sname) + " {\n";
+  s += "  static constexpr int Q = " + std::to_string(Q) + ";\n";
+  s += "  static constexpr int orbits = " + std::to_string(plans.size()) + ";\n";
+  const std::string nb3 = std::to_string(RLBM_NB3);
+  // moments
+  em.out.clear();
+  for (auto& pl : plans) {
+    const int n = (int)pl.members.size();
+    em.line("{  // orbit of population " + std::to_string(pl.members[0]) + " (" + std::to_string(n) + ")");
+    std::vector<Val> v(n);
+    for (int i = 0; i < n; ++i) {
+      v[i].zero = false;
+      v[i].name = "f[" + std::to_string(pl.members[i]) + "]";
+    }
+    for (auto& q : pl.bm) {
+      const Val x = v[q.first], y = v[q.second];
+      v[q.first] = em.addsub(x, y, false);
+      v[q.second] = em.addsub(x, y, true);
+    }
+    for (int o = 0; o < n; ++o)
+      for (int k = 0; k < RLBM_NB3; ++k) {
+        if (pl.Cm[o][k] == 0 || v[o].zero) continue;
+        const ld c = v[o].neg ? -pl.Cm[o][k] : pl.Cm[o][k];
+        em.line("m[" + std::to_string(k) + "] = fmaf(" + v[o].name + ", " + flit(hi_of(c)) + ", m[" +
+                std::to_string(k) + "]);");
+        const ld cl = lo_of(c, split);
+        if (cl != 0)
+          em.line("ml[" + std::to_string(k) + "] = fmaf(" + v[o].name + ", " + flit(cl) + ", ml[" +
+                  std::to_string(k) + "]);");
+      }
+    em.line("}");
+  }
+  s += "  static __device__ __forceinline__ void moments(const float (&f)[" + std::to_string(Q) + "], float (&m)[" +
+       nb3 + "], float (&ml)[" + nb3 + "]) {\n" + em.out + "  }\n";
+  // equilibrium, relaxation and stores, one orbit at a time
+  em.out.clear();
+  for (auto& pl : plans) {
+    const int n = (int)pl.members.size();
+    em.line("{  // orbit of population " + std::to_string(pl.members[0]) + " (" + std::to_string(n) + ")");
+    auto chain = [&](bool lo, std::vector<Val>& g) {
+      for (int o = 0; o < n; ++o) {
+        std::string e;
+        for (int k = 0; k < RLBM_NB3; ++k) {
+          if (pl.Ce[o][k] == 0) continue;
+          const ld c = lo ? lo_of(pl.Ce[o][k], split) : hi_of(pl.Ce[o][k]);
+          if (c == 0) continue;
+          if (e.empty()) e = "nb[" + std::to_string(k) + "] * " + flit(c);
+          else e = "fmaf(nb[" + std::to_string(k) + "], " + flit(c) + ", " + e + ")";
+        }
+        if (e.empty()) continue;
+        g[o].zero = false;
+        g[o].name = em.fresh(lo ? "gl" : "g");
+        em.line("const float " + g[o].name + " = " + e + ";");
+      }
+      for (int i = (int)pl.be.size() - 1; i >= 0; --i) {
+        const int x = pl.be[i].first, y = pl.be[i].second;
+        const Val a = g[x], b = g[y];
+        g[x] = em.addsub(a, b, false);
+        g[y] = em.addsub(a, b, true);
+      }
+    };
+    std::vector<Val> g(n), gl(n);
+    chain(false, g);
+    chain(true, gl);
+    auto ref = [](const Val& v) { return v.zero ? std::string("0.0f") : (v.neg ? "(-" + v.name + ")" : v.name); };
+    for (int i = 0; i < n; ++i) {
+      const int j = pl.members[i];
+      std::string om = "W0";
+      if (t.nz[j] != 0) om = "fmaf(WZ, " + flit((ld)t.nz[j]) + ", " + om + ")";
+      if (t.ny[j] != 0) om = "fmaf(WY, " + flit((ld)t.ny[j]) + ", " + om + ")";
+      if (t.nx[j] != 0) om = "fmaf(WX, " + flit((ld)t.nx[j]) + ", " + om + ")";
+      const std::string fj = "f[" + std::to_string(j) + "]";
+      std::string diff = fj + " - " + ref(g[i]);
+      if (!gl[i].zero) diff = "(" + diff + ") - " + ref(gl[i]);
+      em.line(fj + " = fmaf(-(" + om + "), " + diff + ", " + fj + ");");
+      em.line("st.template put<" + std::to_string(j) + ">(" + fj + ");");
+    }
+    em.line("}");
+  }
+  s += "  template <class Store>\n  static __device__ __forceinline__ void collide(float (&f)[" + std::to_string(Q) +
+       "], const float (&nb)[" + nb3 + "], float W0, float WX, float WY, float WZ, Store& st) {\n" + em.out +
+       "  }\n";
+  s += "};\n";
+  return s;
+}
+
+// The 3D stencils of the configured workloads (G1..G6 at mbar = 5 and the
+// mbar = 1 stencil), at the v0 the workloads use.
+static const Fixed kFixed3[] = {
+    {"zeta5", {0, 0, 0, 1, 0, 0, 1, 1, 0, 1, 1, 1, 2, 0, 0, 2, 1, 0}, 5.0, 0.398},
+    {"zeta1", {0, 0, 0, 2, 0, 0, 3, 0, 0, 3, 2, 0, 3, 2, 2, 4, 0, 0}, 1.0, 0.2403918860},
+};
+
 int main(int argc, char** argv) {
   if (argc != 2) {
     fprintf(stderr, "usage: %s output.h\n", argv[0]);
@@ -429,7 +581,7 @@ int main(int argc, char** argv) {
   }
   std::string out;
   out += "// Generated at build time by gen_fixed_stencils.cpp from the library's own\n";
-  out += "// class tables: straight-line class loops of the configured 2D stencils.\n";
+  out += "// class tables: straight-line class loops of the configured 2D and 3D stencils.\n";
   out += "#pragma once\n#include <stdint.h>\n\nnamespace rlbm_fixed {\n\n";
   std::string table = "static const struct { const char* name; int precision; uint64_t fingerprint; } kFixedTables[] = {\n";
   int id = 0;
@@ -466,7 +618,43 @@ int main(int argc, char** argv) {
   }
   table += "};\nconstexpr int kNumFixed = " + std::to_string(id) + ";\n";
   table += "// X(id, struct, precision) for every generated kernel\n#define RLBM_FIXED_KERNELS(X)" + dispatch + "\n";
-  out += table + "\n}  // namespace rlbm_fixed\n";
+  // 3D stencils: moments and collision of every population
+  std::string table3 = "static const struct { const char* name; int precision; uint64_t fingerprint; } kFixed3Tables[] = {\n";
+  std::string dispatch3;
+  int id3 = 0;
+  for (const Fixed& f : kFixed3) {
+    for (int prec : {RLBM_FP32_DEV, RLBM_FP16_DEV}) {
+      rlbm_stencil_desc d;
+      memset(&d, 0, sizeof d);
+      d.dim = 3;
+      d.n_groups = 6;
+      d.group_base = f.base;
+      d.zeta = f.zeta;
+      d.v0 = f.v0;
+      d.precision = prec;
+      std::unique_ptr<RlbmTable> t(new RlbmTable);
+      rlbm_stencil_info info;
+      char err[512];
+      if (rlbm_build_table(&d, &info, t.get(), err, sizeof err) != RLBM_OK) {
+        fprintf(stderr, "%s (3D): %s\n", f.name, err);
+        return 1;
+      }
+      char sname[64];
+      snprintf(sname, sizeof sname, "T%d", id3);
+      out += "// " + std::string(f.name) + " 3D" + (prec == RLBM_FP32_DEV ? ", float32" : ", float16") + " storage\n";
+      out += gen_struct3(sname, *t);
+      out += "\n";
+      char row[256];
+      snprintf(row, sizeof row, "    {\"%s\", %d, 0x%016llxull},\n", f.name, prec,
+               (unsigned long long)rlbm_table_fingerprint(t.get()));
+      table3 += row;
+      dispatch3 += " X(" + std::to_string(id3) + ", " + sname + ", " + std::to_string(prec) + ")";
+      ++id3;
+    }
+  }
+  table3 += "};\nconstexpr int kNumFixed3 = " + std::to_string(id3) + ";\n";
+  table3 += "// X(id, struct, precision) for every generated 3D kernel\n#define RLBM_FIXED3_KERNELS(X)" + dispatch3 + "\n";
+  out += table + "\n" + table3 + "\n}  // namespace rlbm_fixed\n";
   FILE* fp = fopen(argv[1], "w");
   if (!fp) {
     perror(argv[1]);

@@ -716,9 +716,29 @@ template <> struct Rows3<RLBM_FP16_DEV> : Rows3<RLBM_FP32_DEV> {};
 
 constexpr int step3_waves(int qn, int p) { return p == RLBM_FP64 ? (qn <= 60 ? 2 : 1) : (qn <= 60 ? 3 : 2); }
 
-template <int QN, int QMIN, int P>
+// Store of the post-collision value of population J for the generated 3D
+// code (float32 or float16 storage), at the offset-table entry of J.
+template <int P>
+struct TileStore3 {
+  __amdgpu_buffer_rsrc_t r;
+  int vst;
+  const __attribute__((address_space(4))) unsigned* own;
+  template <int J>
+  __device__ __forceinline__ void put(float v) {
+    if constexpr (P == RLBM_FP32_DEV)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vst, own[J], 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, (_Float16)v), r, vst, own[J], 0);
+  }
+};
+
+// Fx: generated sign-orbit code of a configured 3D stencil (float32 or
+// float16 storage; rlbm_fixed_stencils.h), or void for the table-driven
+// class loops.
+template <int QN, int QMIN, int P, class Fx = void>
 __global__ void __launch_bounds__(kStepBlock) __attribute__((amdgpu_waves_per_eu(step3_waves(QN, P))))
 k_step3(RlbmStepArgs a) {
+  constexpr bool kFixed = !std::is_same<Fx, void>::value;
   using S = typename Traits<P>::S;
   using A = typename Traits<P>::A;
   typedef const __attribute__((address_space(4))) unsigned* OffPtr;
@@ -766,7 +786,11 @@ k_step3(RlbmStepArgs a) {
   A m[RLBM_NB3], ml[RLBM_NB3];
 #pragma unroll
   for (int k = 0; k < RLBM_NB3; ++k) m[k] = ml[k] = A(0);
-  {
+  if constexpr (kFixed) {
+#pragma unroll
+    for (int j = 0; j < QN; ++j) f[j] = (A)raw[j];
+    Fx::moments(f, m, ml);
+  } else {
     const auto* rows = Rows3<P>::m(tb);
     const auto* rows_lo = Rows3<P>::ml(tb);
     typename Rows3<P>::M cur = load_row(rows);
@@ -828,7 +852,10 @@ k_step3(RlbmStepArgs a) {
   const A W0 = (A)w0, WX = (A)(-w0 * v0 * u[0]), WY = (A)(-w0 * v0 * u[1]), WZ = (A)(-w0 * v0 * u[2]);
 
   // equilibrium (eq. mj-discrete-feq, all 14 polynomials) and relaxation
-  {
+  if constexpr (kFixed) {
+    TileStore3<P> st{rs_st, vst, own};
+    Fx::collide(f, nb, W0, WX, WY, WZ, st);
+  } else {
     const auto* rows = Rows3<P>::e(tb);
     const auto* rows_lo = Rows3<P>::el(tb);
     typename Rows3<P>::E cur = load_row(rows);
@@ -1275,6 +1302,19 @@ StepFn select_step3(int prec, int Q) {
   }
 }
 
+// Generated 3D kernels, by id (see rlbm_fixed_stencils.h).
+StepFn fixed3_step(int id) {
+  switch (id) {
+#define RLBM_FIXED3_CASE(ID, ST, PREC) \
+  case ID:                             \
+    return k_step3<rlbm_fixed::ST::Q, rlbm_fixed::ST::Q, PREC, rlbm_fixed::ST>;
+    RLBM_FIXED3_KERNELS(RLBM_FIXED3_CASE)
+#undef RLBM_FIXED3_CASE
+    default:
+      return nullptr;
+  }
+}
+
 // Diagnostic: the network's guess (eps, ux, uy) for the current state, from the
 // same in-kernel inference as the step (one wave per 64 consecutive sites).
 __global__ void __launch_bounds__(kBlock) k_guess(RlbmStepArgs a, float* __restrict__ out) {
@@ -1341,6 +1381,7 @@ struct rlbm_ctx {
   size_t warm_cap = 0;              // floats allocated at d_warm
   bool warm = false;
   int fixed_id = -1;                // generated fixed-stencil kernel for this table, or -1
+  int fixed3_id = -1;               // generated 3D kernel for this table, or -1
   int variant = RLBM_STEP_AUTO;     // RLBM_STEP_AUTO or RLBM_STEP_TABLE
   char err[512] = {0};
 };
@@ -1379,6 +1420,11 @@ extern "C" int rlbm_init_stencil(rlbm_ctx** out, const rlbm_stencil_desc* desc, 
   for (int i = 0; i < rlbm_fixed::kNumFixed && c->h_tab->c.order == 2; ++i)
     if (rlbm_fixed::kFixedTables[i].fingerprint == fp && rlbm_fixed::kFixedTables[i].precision == c->h_tab->c.precision)
       c->fixed_id = i;
+  c->fixed3_id = -1;
+  for (int i = 0; i < rlbm_fixed::kNumFixed3 && c->h_tab->c.order == 2 && c->h_tab->c.dim == 3; ++i)
+    if (rlbm_fixed::kFixed3Tables[i].fingerprint == fp &&
+        rlbm_fixed::kFixed3Tables[i].precision == c->h_tab->c.precision)
+      c->fixed3_id = i;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->d_tab, sizeof(RlbmTable));
   if (e == hipSuccess) e = hipMemcpy(c->d_tab, c->h_tab, sizeof(RlbmTable), hipMemcpyHostToDevice);
@@ -1746,6 +1792,7 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   }
   const bool d3 = layout3(c->h_tab->c);
   StepFn fn = (!d3 && c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? fixed_step(c->fixed_id, g) : nullptr;
+  if (!fn && d3 && c->variant == RLBM_STEP_AUTO && c->fixed3_id >= 0) fn = fixed3_step(c->fixed3_id);
   if (!fn && c->h_tab->c.order == 3) {
     const int dim = c->h_tab->c.dim;
     if (c->h_tab->c.precision == RLBM_FP32_DEV)
@@ -1873,6 +1920,8 @@ extern "C" int rlbm_set_step_variant(rlbm_ctx* c, int variant) {
 extern "C" int rlbm_step_kernel(const rlbm_ctx* c) {
   if (!c) return RLBM_EINVAL;
   const bool g = c->guess != nullptr && c->h_tab->c.precision == RLBM_FP32_DEV;
+  if (c->variant == RLBM_STEP_AUTO && layout3(c->h_tab->c))
+    return c->fixed3_id >= 0 ? RLBM_STEP_FIXED : RLBM_STEP_TABLE;
   return (c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0 && fixed_step(c->fixed_id, g)) ? RLBM_STEP_FIXED
                                                                                           : RLBM_STEP_TABLE;
 }

@@ -1141,6 +1141,18 @@ uint64_t rlbm_table_fingerprint(const RlbmTable* t) {
   mix(cs, sizeof cs);
   mix(c.ref_mom, sizeof c.ref_mom);
   mix(c.nb_ref, sizeof c.nb_ref);
+  if (c.dim == 3) {
+    // rows and constants of the 3D step
+    mix(t->nz, sizeof(int) * Q);
+    for (int j = 0; j < Q; ++j) {
+      mix(t->rowm3f[j], sizeof(float) * RLBM_NB3);
+      mix(t->rowm3f_lo[j], sizeof(float) * RLBM_NB3);
+      mix(t->row3f[j], sizeof(float) * (RLBM_R3_NZ + 1));
+      mix(t->row3f_lo[j], sizeof(float) * RLBM_NB3);
+    }
+    mix(c.ref_mom3, sizeof c.ref_mom3);
+    mix(c.nb_ref3, sizeof c.nb_ref3);
+  }
   return h;
 }
 

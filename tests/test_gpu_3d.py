@@ -152,3 +152,48 @@ def test_3d_entry_points_reject_mismatched_dimension():
     assert L.rlbm_init_fields3(s3.ctx, ctypes.byref(lat), *[t.data_ptr() for t in f], pa.data_ptr(), pb.data_ptr(),
                                nb, None) == rlbm.RLBM_OK
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name,precision", [("zeta5", "fp32"), ("zeta5", "fp16"), ("zeta1", "fp32"),
+                                            ("zeta1", "fp16")])
+def test_3d_generated_kernel_matches_table_kernel(name, precision):
+    """The generated sign-orbit kernel of a configured 3D stencil against the
+    table-driven 3D kernel on the same input (70 x 5 x 6, periodic, 6
+    steps): selected automatically, equal to the storage precision's
+    rounding (the orbit sums round differently)."""
+    from paper_1703_04605_amd import rlbm
+    from tests.helpers import to_dev
+    st = workloads.STENCILS[name]
+    fields = smooth3(6, 5, 70, seed=16)
+    out = {}
+    for variant in ("auto", "table"):
+        s = rlbm.Solver3D(st["bases"], st["zeta"], st["v0"], precision=precision)
+        s.init_fields(*to_dev(fields), tau=0.9)
+        s.set_step_variant(variant)
+        kernel = s.step_kernel()
+        s.step(6)
+        out[variant] = ({k: v.cpu().numpy() for k, v in s.moments(raw=True).items()}, kernel, s.health())
+        del s
+    (a, ka, ha), (b, kb, hb) = out["auto"], out["table"]
+    assert ka == "fixed" and kb == "table"
+    assert ha["flags"] == 0 and hb["flags"] == 0
+    tol = 2e-6 if precision == "fp32" else 2e-3
+    e = errs(a, b, ("n", "eps", "T", "P"))
+    assert max(e.values()) < tol, e
+    # velocity components against the largest speed component (rounding moves
+    # every component by the same absolute amount)
+    speed = max(np.abs(b[k]).max() for k in ("ux", "uy", "uz"))
+    for k in ("ux", "uy", "uz"):
+        assert np.abs(a[k] - b[k]).max() / speed < tol, k
+
+
+def test_3d_zeta1_fp32_vs_oracle():
+    """The zeta = 1 stencil (67 populations) in float32 storage through the
+    generated kernel against the oracle, 8 steps, <= 1e-5."""
+    st = workloads.STENCILS["zeta1"]
+    fields = smooth3(6, 7, 70, seed=17)
+    g, h = gpu3(st, fields, 8, "fp32")
+    r = oracle3(st, fields, 8)
+    e = errs(g, r)
+    assert h["flags"] == 0, h
+    assert max(e.values()) < 1e-5, e
