@@ -277,6 +277,11 @@ int rlbm_moments3(rlbm_ctx* ctx, double* n, double* eps, double* T, double* P, d
  * Third-order stencils (order 3) take the equilibrium of eq.
  * mj-projected-distribution at N = 3 instead (30 polynomials).
  * Asynchronous on stream; launch errors are returned at once (RLBM_EHIP).
+ * Issues kernel launches only (no allocation, memset, copy or
+ * synchronisation), so the steps can be recorded by stream capture and
+ * replayed; the context's step count and current buffer advance when the
+ * steps are recorded, so a recording holds an even number of steps and
+ * starts after the first step.
  * Health flags accumulate on the device: the call returns before any site
  * is computed, so a fatal flag is reported by rlbm_get_health (RLBM_ENUMERIC)
  * and not by this call; RLBM_ESTATE before rlbm_init_fields.
