@@ -80,6 +80,7 @@ struct Val {
 struct Emitter {
   std::string out;
   int tmp = 0;
+  std::string type = "float";  // arithmetic type of the emitted temporaries
   void line(const std::string& s) { out += "    " + s + "\n"; }
   std::string fresh(const char* p) { return std::string(p) + std::to_string(tmp++); }
   // a + s b with symbolic zeros
@@ -100,7 +101,7 @@ struct Emitter {
       e = a.name + " + " + nb.name;
       r.neg = true;
     }
-    line("const float " + r.name + " = " + e + ";");
+    line("const " + type + " " + r.name + " = " + e + ";");
     return r;
   }
   // in-place fast Walsh-Hadamard transform (Sylvester order)
@@ -567,6 +568,139 @@ static std::string gen_struct3(const char* sname, const RlbmTable& t) {
   return s;
 }
 
+// Third order (Sec. III.A, III.D): the two passes of the third-order step
+// for one stencil, orbit by orbit.  Pass 1 pulls an orbit's populations and
+// adds their 14 moment monomials (the ones that can be nonzero on a lattice
+// of this dimension); pass 2 pulls them again, forms their equilibria from
+// the 30 projections on the centred monomials (the active ones, in the
+// table's packed order), relaxes and stores.  Float64 storage takes double
+// coefficients; float32 deviation storage hi/lo float pairs as above.
+static std::string dlit_any(ld x, bool dbl) { return dbl ? dlit((double)x) : flit(x); }
+
+static std::string gen_struct_o3(const char* sname, const RlbmTable& t) {
+  const int Q = t.c.Q, dim = t.c.dim;
+  const bool dbl = t.c.precision == RLBM_FP64;
+  const bool split = t.c.precision == RLBM_FP32_DEV;
+  const O3Act& act = kO3Act[dim];
+  std::vector<OrbitPlan> plans;
+  for (auto& o : (dim == 3 ? orbits3(t) : orbits(t))) {
+    std::vector<std::vector<ld>> Rm, Re;
+    for (int j : o) {
+      std::vector<ld> rm(RLBM_NB3, 0), re(act.n);
+      for (int k = 0; k < RLBM_NB3; ++k)
+        if (o3_mom_active(dim, k))
+          rm[k] = dbl ? (ld)t.rowm3d[j][k] : (ld)t.rowm3f[j][k] + (ld)t.rowm3f_lo[j][k];
+      for (int k = 0; k < act.n; ++k) re[k] = dbl ? (ld)t.rowo3[j][k] : (ld)t.rowo3f[j][k] + (ld)t.rowo3f_lo[j][k];
+      Rm.push_back(rm);
+      Re.push_back(re);
+    }
+    plans.push_back(plan_rows(o, Rm, Re));
+  }
+  const std::string A = dbl ? "double" : "float";
+  const std::string fma = dbl ? "fma" : "fmaf";
+  auto hi = [&](ld c) { return dbl ? c : hi_of(c); };
+  auto lo = [&](ld c) { return dbl ? 0.0L : lo_of(c, split); };
+  Emitter em;
+  em.type = A;
+  std::string s;
+  s += "struct " + std::string(sname) + " {\n";
+  s += "  static constexpr int Q = " + std::to_string(Q) + ";\n";
+  s += "  static constexpr int orbits = " + std::to_string(plans.size()) + ";\n";
+  // pass 1
+  em.out.clear();
+  for (auto& pl : plans) {
+    const int n = (int)pl.members.size();
+    em.line("{  // orbit of class " + std::to_string(pl.members[0]) + " (" + std::to_string(n) + ")");
+    std::vector<Val> v(n);
+    for (int i = 0; i < n; ++i) {
+      v[i].zero = false;
+      v[i].name = "f" + std::to_string(pl.members[i]);
+      em.line("const " + A + " " + v[i].name + " = pl.template get<" + std::to_string(pl.members[i]) + ">();");
+    }
+    for (auto& q : pl.bm) {
+      const Val x = v[q.first], y = v[q.second];
+      v[q.first] = em.addsub(x, y, false);
+      v[q.second] = em.addsub(x, y, true);
+    }
+    for (int o = 0; o < n; ++o)
+      for (int k = 0; k < RLBM_NB3; ++k) {
+        if (pl.Cm[o][k] == 0 || v[o].zero) continue;
+        const ld c = v[o].neg ? -pl.Cm[o][k] : pl.Cm[o][k];
+        em.line("m[" + std::to_string(k) + "] = " + fma + "(" + v[o].name + ", " + dlit_any(hi(c), dbl) + ", m[" +
+                std::to_string(k) + "]);");
+        const ld cl = lo(c);
+        if (cl != 0)
+          em.line("ml[" + std::to_string(k) + "] = fmaf(" + v[o].name + ", " + flit(cl) + ", ml[" +
+                  std::to_string(k) + "]);");
+      }
+    em.line("}");
+    em.line("__builtin_amdgcn_sched_barrier(0);");
+  }
+  s += "  template <class Pull>\n  static __device__ __forceinline__ void moments(Pull& pl, " + A + " (&m)[" +
+       std::to_string(RLBM_NB3) + "], " + A + " (&ml)[" + std::to_string(RLBM_NB3) + "]) {\n" + em.out + "  }\n";
+  // pass 2
+  em.out.clear();
+  for (auto& pl : plans) {
+    const int n = (int)pl.members.size();
+    em.line("{  // orbit of class " + std::to_string(pl.members[0]) + " (" + std::to_string(n) + ")");
+    for (int i = 0; i < n; ++i)
+      em.line("const " + A + " f" + std::to_string(pl.members[i]) + " = pl.template get<" +
+              std::to_string(pl.members[i]) + ">();");
+    auto chain = [&](bool low, std::vector<Val>& g) {
+      for (int o = 0; o < n; ++o) {
+        std::string e;
+        for (int k = 0; k < act.n; ++k) {
+          if (pl.Ce[o][k] == 0) continue;
+          const ld c = low ? lo(pl.Ce[o][k]) : hi(pl.Ce[o][k]);
+          if (c == 0) continue;
+          const std::string mk = "M[" + std::to_string((int)act.m[k]) + "]";
+          if (e.empty()) e = mk + " * " + dlit_any(c, dbl);
+          else e = fma + "(" + mk + ", " + dlit_any(c, dbl) + ", " + e + ")";
+        }
+        if (e.empty()) continue;
+        g[o].zero = false;
+        g[o].name = em.fresh(low ? "gl" : "g");
+        em.line("const " + A + " " + g[o].name + " = " + e + ";");
+      }
+      for (int i = (int)pl.be.size() - 1; i >= 0; --i) {
+        const int x = pl.be[i].first, y = pl.be[i].second;
+        const Val a = g[x], b = g[y];
+        g[x] = em.addsub(a, b, false);
+        g[y] = em.addsub(a, b, true);
+      }
+    };
+    std::vector<Val> g(n), gl(n);
+    chain(false, g);
+    if (split) chain(true, gl);
+    const std::string zero = dbl ? "0.0" : "0.0f";
+    auto ref = [&](const Val& v) { return v.zero ? zero : (v.neg ? "(-" + v.name + ")" : v.name); };
+    for (int i = 0; i < n; ++i) {
+      const int j = pl.members[i];
+      std::string om = "W0";
+      if (t.nz[j] != 0) om = fma + "(WZ, " + dlit_any((ld)t.nz[j], dbl) + ", " + om + ")";
+      if (t.ny[j] != 0) om = fma + "(WY, " + dlit_any((ld)t.ny[j], dbl) + ", " + om + ")";
+      if (t.nx[j] != 0) om = fma + "(WX, " + dlit_any((ld)t.nx[j], dbl) + ", " + om + ")";
+      const std::string fj = "f" + std::to_string(j);
+      std::string diff = fj + " - " + ref(g[i]);
+      if (split && !gl[i].zero) diff = "(" + diff + ") - " + ref(gl[i]);
+      em.line("st.template put<" + std::to_string(j) + ">(" + fma + "(-(" + om + "), " + diff + ", " + fj + "));");
+    }
+    em.line("}");
+    em.line("__builtin_amdgcn_sched_barrier(0);");
+  }
+  s += "  template <class Pull, class Store>\n  static __device__ __forceinline__ void collide(Pull& pl, const " + A +
+       " (&M)[" + std::to_string(RLBM_NO3) + "], " + A + " W0, " + A + " WX, " + A + " WY, " + A + " WZ, Store& st) {\n" +
+       em.out + "  }\n";
+  s += "};\n";
+  return s;
+}
+
+// The third-order stencil of Fig. 2b (groups G1, G2, G3, G4, G5, G8, G9,
+// G10, G12, G13, G15) at mbar = 7.5 with the library's own v0 (middle of the
+// positive-weight window), for 2D (merged classes) and 3D lattices.
+static const int kFig2b[33] = {0, 0, 0, 1, 0, 0, 1, 1, 0, 1, 1, 1, 2, 0, 0, 2, 1, 1, 2, 2, 1,
+                               2, 2, 2, 3, 1, 0, 3, 2, 0, 3, 1, 1};
+
 // The 3D stencils of the configured workloads (G1..G6 at mbar = 5 and the
 // mbar = 1 stencil), at the v0 the workloads use.
 static const Fixed kFixed3[] = {
@@ -652,9 +786,54 @@ int main(int argc, char** argv) {
       ++id3;
     }
   }
+  // third order: the Fig. 2b stencil at mbar = 7.5
+  std::string tableo3 =
+      "static const struct { const char* name; int precision; int dim; uint64_t fingerprint; } kFixedO3Tables[] = {\n";
+  std::string dispatcho3;
+  int ido3 = 0;
+  // (the 3D float64 step keeps the table-driven passes: its generated code
+  // needs more registers than one wave per SIMD leaves room for)
+  const int o3cases[3][2] = {{2, RLBM_FP64}, {2, RLBM_FP32_DEV}, {3, RLBM_FP32_DEV}};
+  for (const auto& oc : o3cases) {
+    {
+      const int dim = oc[0], prec = oc[1];
+      rlbm_stencil_desc d;
+      memset(&d, 0, sizeof d);
+      d.dim = dim;
+      d.order = 3;
+      d.n_groups = 11;
+      d.group_base = kFig2b;
+      d.zeta = 7.5;
+      d.v0 = 0.0;
+      d.precision = prec;
+      std::unique_ptr<RlbmTable> t(new RlbmTable);
+      rlbm_stencil_info info;
+      char err[512];
+      if (rlbm_build_table(&d, &info, t.get(), err, sizeof err) != RLBM_OK) {
+        fprintf(stderr, "third order (%dD): %s\n", dim, err);
+        return 1;
+      }
+      char sname[64];
+      snprintf(sname, sizeof sname, "U%d", ido3);
+      out += "// third order, Fig. 2b stencil, " + std::to_string(dim) + "D" +
+             (prec == RLBM_FP64 ? ", float64" : ", float32") + " storage\n";
+      out += gen_struct_o3(sname, *t);
+      out += "\n";
+      char row[256];
+      snprintf(row, sizeof row, "    {\"fig2b\", %d, %d, 0x%016llxull},\n", prec, dim,
+               (unsigned long long)rlbm_table_fingerprint(t.get()));
+      tableo3 += row;
+      dispatcho3 += " X(" + std::to_string(ido3) + ", " + sname + ", " + std::to_string(prec) + ", " +
+                    std::to_string(dim) + ")";
+      ++ido3;
+    }
+  }
+  tableo3 += "};\nconstexpr int kNumFixedO3 = " + std::to_string(ido3) + ";\n";
+  tableo3 += "// X(id, struct, precision, dim) for every generated third-order kernel\n#define RLBM_FIXEDO3_KERNELS(X)" +
+             dispatcho3 + "\n";
   table3 += "};\nconstexpr int kNumFixed3 = " + std::to_string(id3) + ";\n";
   table3 += "// X(id, struct, precision) for every generated 3D kernel\n#define RLBM_FIXED3_KERNELS(X)" + dispatch3 + "\n";
-  out += table + "\n" + table3 + "\n}  // namespace rlbm_fixed\n";
+  out += table + "\n" + table3 + "\n" + tableo3 + "\n}  // namespace rlbm_fixed\n";
   FILE* fp = fopen(argv[1], "w");
   if (!fp) {
     perror(argv[1]);

@@ -923,11 +923,57 @@ constexpr int kO3Chunk = 8;
 // P: float64 storage, or float32 deviations d = f - f^ref (sums in float32
 // over hi + lo rows, the reference's moments and projections added in
 // float64, as in the second-order float32 step).
-template <int D, int P>
-__global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
+// Pulls and stores of the generated third-order code (by class index, at
+// the offset-table entries; stores also write the ghost copies near the
+// lattice edges).
+template <int P>
+struct PullO3 {
+  using A = typename Traits<P>::A;
+  __amdgpu_buffer_rsrc_t r;
+  int vld;
+  const __attribute__((address_space(4))) unsigned* pull;
+  template <int J>
+  __device__ __forceinline__ A get() const {
+    if constexpr (P == RLBM_FP32_DEV)
+      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vld, pull[J], 0));
+    else
+      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vld, pull[J], 0));
+  }
+};
+template <int P>
+struct StoreO3 {
+  using A = typename Traits<P>::A;
+  using S = typename Traits<P>::S;
+  __amdgpu_buffer_rsrc_t r;
+  int vst;
+  const __attribute__((address_space(4))) unsigned* own;
+  bool ghosts;  // the tile touches a lattice edge and the lane holds a site
+  S* dst;
+  RlbmLayout L;
+  int x, y, z;
+  unsigned xm, ym, zm;
+  template <int J>
+  __device__ __forceinline__ void put(A v) {
+    if constexpr (P == RLBM_FP32_DEV)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vst, own[J], 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U32x2, v), r, vst, own[J], 0);
+    if (ghosts) store_ghosts3(dst + (long long)J * L.cs, L, x, y, z, xm, ym, zm, (S)v);
+  }
+};
+
+// Fx: generated orbit code of the configured third-order stencil
+// (rlbm_fixed_stencils.h), or void for the table-driven passes.  The
+// generated float32 code is held to four waves per SIMD (it would otherwise
+// take up to 157 registers per lane for the orbits' straight-line code).
+template <int D, int P, class Fx = void>
+__global__ void __launch_bounds__(kStepBlock)
+    __attribute__((amdgpu_waves_per_eu((!std::is_same<Fx, void>::value && P == RLBM_FP32_DEV) ? 4 : 1)))
+    k_step_o3(RlbmStepArgs a) {
   typedef const __attribute__((address_space(4))) unsigned* OffPtr;
   using S = typename Traits<P>::S;
   using A = typename Traits<P>::A;
+  constexpr bool kFixed = !std::is_same<Fx, void>::value;
   constexpr bool kF32 = P == RLBM_FP32_DEV;
   const TabPtr tb = as_tab(a.tab);
   const RlbmLayout& L = a.L;
@@ -965,6 +1011,10 @@ __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
   A m[RLBM_NB3], ml[RLBM_NB3];
 #pragma unroll
   for (int k = 0; k < RLBM_NB3; ++k) m[k] = ml[k] = A(0);
+  if constexpr (kFixed) {
+    PullO3<P> pl{rs_ld, vld, pull};
+    Fx::moments(pl, m, ml);
+  } else {
   for (int j0 = 0; j0 < Q; j0 += kO3Chunk) {
     A f[kO3Chunk];
 #pragma unroll
@@ -986,6 +1036,7 @@ __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
       // (keeps the scalar row loads of later classes from piling up in SGPRs)
       __builtin_amdgcn_sched_barrier(0);
     }
+  }
   }
   double md[RLBM_NB3];
 #pragma unroll
@@ -1022,6 +1073,16 @@ __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
   const bool ghosts = xedge || ym != 0u || zm != 0u;
   const unsigned xm = xedge ? ghost_mask(x, L.nx, L.Sx, L.bc_x) : 0u;
   S* __restrict__ dst = (S*)a.dst;
+  if constexpr (kFixed) {
+    // an opaque copy of the lane offset, so that the second pulls are not
+    // merged with the first ones (which would keep every population in
+    // registers across the Landau solve)
+    int vld2 = vld;
+    asm volatile("" : "+v"(vld2));
+    PullO3<P> pl{rs_ld, vld2, pull};
+    StoreO3<P> st{rs_st, vst, own, ghosts && active, dst, L, x, y, z, xm, ym, zm};
+    Fx::collide(pl, M, W0, WX, WY, WZ, st);
+  } else {
   for (int j0 = 0; j0 < Q; j0 += kO3Chunk) {
     A f[kO3Chunk];
 #pragma unroll
@@ -1063,6 +1124,7 @@ __global__ void __launch_bounds__(kStepBlock) k_step_o3(RlbmStepArgs a) {
       if (ghosts && active) store_ghosts3(dst + (long long)j * L.cs, L, x, y, z, xm, ym, zm, (S)out);
       __builtin_amdgcn_sched_barrier(0);
     }
+  }
   }
   wave_stats(a.slots, t, active ? flags : 0u, active ? (unsigned)iters : 0u, active ? (unsigned)iters : 0u);
 }
@@ -1302,6 +1364,19 @@ StepFn select_step3(int prec, int Q) {
   }
 }
 
+// Generated third-order kernels, by id (see rlbm_fixed_stencils.h).
+StepFn fixedo3_step(int id) {
+  switch (id) {
+#define RLBM_FIXEDO3_CASE(ID, ST, PREC, DIM) \
+  case ID:                                  \
+    return k_step_o3<DIM, PREC, rlbm_fixed::ST>;
+    RLBM_FIXEDO3_KERNELS(RLBM_FIXEDO3_CASE)
+#undef RLBM_FIXEDO3_CASE
+    default:
+      return nullptr;
+  }
+}
+
 // Generated 3D kernels, by id (see rlbm_fixed_stencils.h).
 StepFn fixed3_step(int id) {
   switch (id) {
@@ -1382,6 +1457,7 @@ struct rlbm_ctx {
   bool warm = false;
   int fixed_id = -1;                // generated fixed-stencil kernel for this table, or -1
   int fixed3_id = -1;               // generated 3D kernel for this table, or -1
+  int fixedo3_id = -1;              // generated third-order kernel for this table, or -1
   int variant = RLBM_STEP_AUTO;     // RLBM_STEP_AUTO or RLBM_STEP_TABLE
   char err[512] = {0};
 };
@@ -1425,6 +1501,12 @@ extern "C" int rlbm_init_stencil(rlbm_ctx** out, const rlbm_stencil_desc* desc, 
     if (rlbm_fixed::kFixed3Tables[i].fingerprint == fp &&
         rlbm_fixed::kFixed3Tables[i].precision == c->h_tab->c.precision)
       c->fixed3_id = i;
+  c->fixedo3_id = -1;
+  for (int i = 0; i < rlbm_fixed::kNumFixedO3 && c->h_tab->c.order == 3; ++i)
+    if (rlbm_fixed::kFixedO3Tables[i].fingerprint == fp &&
+        rlbm_fixed::kFixedO3Tables[i].precision == c->h_tab->c.precision &&
+        rlbm_fixed::kFixedO3Tables[i].dim == c->h_tab->c.dim)
+      c->fixedo3_id = i;
   hipError_t e = hipGetDevice(&c->device);
   if (e == hipSuccess) e = hipMalloc((void**)&c->d_tab, sizeof(RlbmTable));
   if (e == hipSuccess) e = hipMemcpy(c->d_tab, c->h_tab, sizeof(RlbmTable), hipMemcpyHostToDevice);
@@ -1793,6 +1875,8 @@ extern "C" int rlbm_step(rlbm_ctx* c, int nsteps, void* stream) {
   const bool d3 = layout3(c->h_tab->c);
   StepFn fn = (!d3 && c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0) ? fixed_step(c->fixed_id, g) : nullptr;
   if (!fn && d3 && c->variant == RLBM_STEP_AUTO && c->fixed3_id >= 0) fn = fixed3_step(c->fixed3_id);
+  if (!fn && c->h_tab->c.order == 3 && c->variant == RLBM_STEP_AUTO && c->fixedo3_id >= 0)
+    fn = fixedo3_step(c->fixedo3_id);
   if (!fn && c->h_tab->c.order == 3) {
     const int dim = c->h_tab->c.dim;
     if (c->h_tab->c.precision == RLBM_FP32_DEV)
@@ -1921,7 +2005,7 @@ extern "C" int rlbm_step_kernel(const rlbm_ctx* c) {
   if (!c) return RLBM_EINVAL;
   const bool g = c->guess != nullptr && c->h_tab->c.precision == RLBM_FP32_DEV;
   if (c->variant == RLBM_STEP_AUTO && layout3(c->h_tab->c))
-    return c->fixed3_id >= 0 ? RLBM_STEP_FIXED : RLBM_STEP_TABLE;
+    return (c->h_tab->c.order == 3 ? c->fixedo3_id : c->fixed3_id) >= 0 ? RLBM_STEP_FIXED : RLBM_STEP_TABLE;
   return (c->variant == RLBM_STEP_AUTO && c->fixed_id >= 0 && fixed_step(c->fixed_id, g)) ? RLBM_STEP_FIXED
                                                                                           : RLBM_STEP_TABLE;
 }

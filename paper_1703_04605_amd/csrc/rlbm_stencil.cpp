@@ -1153,6 +1153,18 @@ uint64_t rlbm_table_fingerprint(const RlbmTable* t) {
     mix(c.ref_mom3, sizeof c.ref_mom3);
     mix(c.nb_ref3, sizeof c.nb_ref3);
   }
+  if (c.order == 3) {
+    // rows of the third-order step
+    mix(t->nz, sizeof(int) * Q);
+    for (int j = 0; j < Q; ++j) {
+      mix(t->rowm3d[j], sizeof(double) * RLBM_NB3);
+      mix(t->rowm3f[j], sizeof(float) * RLBM_NB3);
+      mix(t->rowm3f_lo[j], sizeof(float) * RLBM_NB3);
+      mix(t->rowo3[j], sizeof(double) * RLBM_ROWO3);
+      mix(t->rowo3f[j], sizeof(float) * RLBM_ROWO3);
+      mix(t->rowo3f_lo[j], sizeof(float) * RLBM_ROWO3);
+    }
+  }
   return h;
 }
 

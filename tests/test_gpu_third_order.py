@@ -235,3 +235,46 @@ def test_third_order_entry_points():
     assert s.population_bytes3(16, 8, 1) > 0 and s.population_bytes3(16, 8, 2) == 0
     L = rlbm.lib()
     assert L.rlbm_population_bytes3(s.ctx, 16, 8, 1) > 0
+
+
+@pytest.mark.parametrize("dim,precision", [(2, "fp64"), (2, "fp32"), (3, "fp32")])
+def test_third_order_generated_kernel(dim, precision):
+    """The paper's third-order stencil with the library's own window and
+    weights (no weights given) runs the generated orbit code: it matches the
+    table-driven passes (float64 to 1e-12, float32 to 2e-6) and the oracle
+    given the library's v0 and weights (1e-12 / 1e-5), 2D 70 x 6 over 6 steps
+    or 3D 70 x 5 x 4 over 4 steps."""
+    from oracle import groups, lattice as L
+    from paper_1703_04605_amd import rlbm
+    from tests.helpers import to_dev
+    bases = groups.bases_of(G3)
+    info = rlbm.solve_stencil(bases, MBAR, 0.0, dim=3, order=3)
+    v0, w = info["v0"], [float(x) for x in info["weights"]]
+    shape, steps = ((1, 6, 70), 6) if dim == 2 else ((4, 5, 70), 4)
+    nz, ny, nx = shape
+    fields = smooth(nz, ny, nx, seed=25, vary_z=dim == 3)
+    if dim == 2:
+        fields = fields[:4] + (np.zeros_like(fields[0]),)
+    bc = ("periodic", "outflow", "periodic")
+    res = {}
+    for variant in ("auto", "table"):
+        s = rlbm.Solver3D(bases, MBAR, 0.0, order=3, dim=dim, precision=precision)
+        s.init_fields(*to_dev(fields), bc=bc, tau=0.9)
+        s.set_step_variant(variant)
+        kernel = s.step_kernel()
+        s.step(steps)
+        res[variant] = ({k: v.cpu().numpy() for k, v in s.moments(raw=True).items()}, kernel, s.health())
+        del s
+    (g, kg, hg), (t, kt, ht) = res["auto"], res["table"]
+    assert kg == "fixed" and kt == "table"
+    assert hg["flags"] == 0 and ht["flags"] == 0
+    keys = FIELDS if dim == 3 else ("n", "eps", "T", "P", "ux", "uy")
+    e = errs(g, t, keys)
+    assert max(e.values()) < (1e-12 if precision == "fp64" else 2e-6), e
+    ps = L.build_stencil(bases, MBAR, v0, mode="full", order=3, weights=w)
+    m = L.Model3D(ps, nx, ny, nz, bc=bc, tau=0.9)
+    m.init_equilibrium(*fields)
+    m.step(steps)
+    e = errs(g, m.fields(), keys)
+    print(e)
+    assert max(e.values()) < (1e-12 if precision == "fp64" else 1e-5), e
