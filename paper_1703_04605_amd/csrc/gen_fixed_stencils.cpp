@@ -791,9 +791,7 @@ int main(int argc, char** argv) {
       "static const struct { const char* name; int precision; int dim; uint64_t fingerprint; } kFixedO3Tables[] = {\n";
   std::string dispatcho3;
   int ido3 = 0;
-  // (the 3D float64 step keeps the table-driven passes: its generated code
-  // needs more registers than one wave per SIMD leaves room for)
-  const int o3cases[3][2] = {{2, RLBM_FP64}, {2, RLBM_FP32_DEV}, {3, RLBM_FP32_DEV}};
+  const int o3cases[4][2] = {{2, RLBM_FP64}, {2, RLBM_FP32_DEV}, {3, RLBM_FP32_DEV}, {3, RLBM_FP64}};
   for (const auto& oc : o3cases) {
     {
       const int dim = oc[0], prec = oc[1];

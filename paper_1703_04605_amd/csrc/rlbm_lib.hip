@@ -964,11 +964,13 @@ struct StoreO3 {
 
 // Fx: generated orbit code of the configured third-order stencil
 // (rlbm_fixed_stencils.h), or void for the table-driven passes.  The
-// generated float32 code is held to four waves per SIMD (it would otherwise
-// take up to 157 registers per lane for the orbits' straight-line code).
+// generated code is held to four waves per SIMD in float32 (it would
+// otherwise take up to 157 registers per lane for the orbits' straight-line
+// code) and to two in 3D float64 (one otherwise); measured, the 2D float64
+// code runs best with its own choice (two waves).
 template <int D, int P, class Fx = void>
 __global__ void __launch_bounds__(kStepBlock)
-    __attribute__((amdgpu_waves_per_eu((!std::is_same<Fx, void>::value && P == RLBM_FP32_DEV) ? 4 : 1)))
+    __attribute__((amdgpu_waves_per_eu(std::is_same<Fx, void>::value ? 1 : (P == RLBM_FP32_DEV ? 4 : (D == 3 ? 2 : 1)))))
     k_step_o3(RlbmStepArgs a) {
   typedef const __attribute__((address_space(4))) unsigned* OffPtr;
   using S = typename Traits<P>::S;

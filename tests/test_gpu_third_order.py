@@ -237,7 +237,7 @@ def test_third_order_entry_points():
     assert L.rlbm_population_bytes3(s.ctx, 16, 8, 1) > 0
 
 
-@pytest.mark.parametrize("dim,precision", [(2, "fp64"), (2, "fp32"), (3, "fp32")])
+@pytest.mark.parametrize("dim,precision", [(2, "fp64"), (2, "fp32"), (3, "fp64"), (3, "fp32")])
 def test_third_order_generated_kernel(dim, precision):
     """The paper's third-order stencil with the library's own window and
     weights (no weights given) runs the generated orbit code: it matches the
