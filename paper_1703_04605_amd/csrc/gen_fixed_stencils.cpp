@@ -1,4 +1,4 @@
-// Build-time generator of the fixed-stencil class kernels.
+// Build-time generator of the fixed-stencil class code.
 //
 // For each stencil of the configured workloads it builds the library's own
 // class table (the same code the library runs at rlbm_init_stencil) and emits
@@ -35,6 +35,10 @@
 // 3D stencils (every population a class of its own) are factored the same
 // way over sign orbits: the populations whose displacements differ only in
 // the signs of their nonzero components (1, 2, 4 or 8 members, see orbits3).
+// The third-order stencil of Fig. 2b (eleven groups at mbar = 7.5) gets the
+// same treatment for its 14 moment monomials and its 30 equilibrium rows in
+// float64 and float32, emitted as the two passes of the third-order step,
+// with the pulls and stores inside each orbit's block (gen_struct_o3).
 //
 // The output also carries each stencil's table fingerprint; the library uses
 // a generated kernel only for a context whose table has the same fingerprint.
